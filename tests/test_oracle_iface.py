@@ -1,0 +1,120 @@
+"""Pins for oracle/iface.py: skeleton M and L, H_theta closed forms, inverse
+Lanczos, face-block preconditioner."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as w
+from oracle import dd, iface, krylov
+
+
+def test_skeleton_element_matrices_closed_form():
+    Me, Le = iface._segment_matrices()
+    assert np.allclose(Me, np.array([[2, 1], [1, 2]]) / 6.0, rtol=0, atol=1e-16)
+    assert np.allclose(Le, np.array([[1, -1], [-1, 1]]), rtol=0, atol=1e-15)
+    Mq, Lq = iface._quad_matrices()
+    Mt = np.array([[4, 2, 1, 2], [2, 4, 2, 1], [1, 2, 4, 2], [2, 1, 2, 4]]) / 36.0
+    Lt = np.array([[4, -1, -2, -1], [-1, 4, -1, -2], [-2, -1, 4, -1],
+                   [-1, -2, -1, 4]]) / 6.0
+    assert np.allclose(Mq, Mt, rtol=0, atol=1e-16)
+    assert np.allclose(Lq, Lt, rtol=0, atol=1e-15)
+
+
+def _unclamped(dim):
+    if dim == 2:
+        p = w.cantilever2d(24, 16, block=8)
+    else:
+        p = w.cantilever3d(8, 8, 6, cuts=(w.even_cuts(8, 4), w.even_cuts(8, 4),
+                                          np.array([0, 3, 6])))
+    p.clamp = 0
+    return p
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_skeleton_measure_and_constants(dim):
+    p = _unclamped(dim)
+    M, L, g = iface.skeleton_matrices(p)
+    one = np.ones(M.shape[0])
+    if dim == 2:
+        # total length of the cut lines
+        meas = (len(p.cuts[0]) - 2) * p.nel[1] + (len(p.cuts[1]) - 2) * p.nel[0]
+    else:
+        nx, ny, nz = p.nel
+        meas = ((len(p.cuts[0]) - 2) * ny * nz + (len(p.cuts[1]) - 2) * nx * nz
+                + (len(p.cuts[2]) - 2) * nx * ny)
+    assert one @ (M @ one) == pytest.approx(meas, rel=1e-14)
+    assert np.abs(L @ one).max() < 1e-13
+    assert abs(M - M.T).max() < 1e-16 and abs(L - L.T).max() < 1e-16
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_skeleton_nodes_are_gamma_and_L_spd(dim):
+    p = w.cantilever2d_uniform_64x32() if dim == 2 else \
+        w.cantilever3d(8, 8, 6, cuts=(w.even_cuts(8, 4), w.even_cuts(8, 4),
+                                      np.array([0, 3, 6])))
+    M, L, g = iface.skeleton_matrices(p)
+    els = iface.skeleton_elements(p)
+    cls = dd.classify(p)
+    sk = np.unique(els)
+    sk = sk[cls[sk] != dd.DIRICHLET]
+    assert np.array_equal(np.sort(sk), np.flatnonzero(cls == dd.GAMMA))
+    assert np.linalg.eigvalsh(L.toarray()).min() > 0
+
+
+def test_htilde_special_cases():
+    p = w.cantilever2d(32, 16, block=8)
+    for lumped in (False, True):
+        M, L, _ = iface.skeleton_matrices(p, lumped=lumped)
+        Md, Ld = M.toarray(), L.toarray()
+        assert np.allclose(iface.htilde(M, L, 1.0), Md, atol=1e-12)
+        assert np.allclose(iface.htilde(M, L, 0.0), Ld, atol=1e-11)
+        H = iface.htilde(M, L, 0.5)
+        X = np.linalg.solve(Md, H)
+        assert np.allclose(X @ X, np.linalg.solve(Md, Ld), atol=1e-9)
+        assert np.allclose(H, H.T, atol=1e-12)
+        assert np.linalg.eigvalsh(0.5 * (H + H.T)).min() > 0
+        Hi = iface.htilde_inv(M, L, 0.3)
+        assert np.allclose(Hi @ iface.htilde(M, L, 0.3), np.eye(len(Md)), atol=1e-8)
+        # H_theta = M + M (M^{-1} L)^{1-theta}
+        Hfull = Md + iface.htilde(M, L, 0.4)
+        assert np.allclose(iface.h_inv(M, L, 0.4) @ Hfull, np.eye(len(Md)), atol=1e-8)
+
+
+def test_inverse_lanczos_converges_to_closed_form():
+    p = w.cantilever2d(32, 16, block=8)
+    M, L, _ = iface.skeleton_matrices(p, lumped=True)
+    rng = np.random.default_rng(0)
+    r = rng.standard_normal(M.shape[0])
+    for theta in (0.5, 0.7):
+        zd = iface.htilde_inv(M, L, theta) @ r
+        errs = []
+        for k in (4, 8, 16, 64):
+            z, kk = iface.inverse_lanczos(M, L, theta, r, kmax=k, tol=0.0)
+            errs.append(np.linalg.norm(z - zd) / np.linalg.norm(zd))
+        assert errs[-1] < 1e-10
+        assert errs[0] > errs[1] > errs[2] > errs[3]
+
+
+def test_face_partition_2d_counts():
+    p = w.cantilever2d_uniform_64x32()
+    faces, rest = iface.face_partition(p)
+    # 3 vertical lines split by the y=16 line into 2 segments each, and the
+    # y=16 line split into 4 segments: 10 faces; 3 interior crossings.
+    assert len(faces) == 10 and len(rest) == 3
+    assert sum(len(f) for f in faces) + len(rest) == 160
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_face_block_pcg_solves_L(dim):
+    p = w.cantilever2d(48, 32, block=16) if dim == 2 else \
+        w.cantilever3d(12, 8, 8, cuts=(w.even_cuts(12, 4), w.even_cuts(8, 4),
+                                       w.even_cuts(8, 4)))
+    M, L, _ = iface.skeleton_matrices(p, lumped=True)
+    B = iface.FaceBlockPreconditioner(p, L)
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(L.shape[0])
+    x, its, _ = krylov.pcg(lambda v: L @ v, b, B.apply, tol=1e-12, maxit=500)
+    xr = spla.spsolve(L.tocsc(), b)
+    assert np.linalg.norm(x - xr) <= 1e-9 * np.linalg.norm(xr)
+    _, its_plain, _ = krylov.pcg(lambda v: L @ v, b, None, tol=1e-12, maxit=2000)
+    assert its < its_plain
