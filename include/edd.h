@@ -1,0 +1,221 @@
+/*
+ * edd.h -- C ABI of the MI355X Schur-interface elasticity solver.
+ *
+ * The library solves the discrete isotropic linear-elasticity system
+ * K(E) u = f of Turner, Kocvara and Loghin (arXiv 1501.06211), Section 2,
+ * eq. (NumberFour), on a structured grid of unit Q1 quadrilaterals (2D,
+ * plane stress) or trilinear hexahedra (3D), by the non-overlapping domain
+ * decomposition of Section 1: interior unknowns of every subdomain are
+ * eliminated with batched direct solves (K_II is the direct sum of the
+ * subdomain blocks, eq. (NumberFive)) and the interface (Schur complement)
+ * system S u_G = f_G - K_GI K_II^{-1} f_I of eq. (3MatSplit) is solved by a
+ * preconditioned Krylov method, optionally with the interface preconditioner
+ * Hhat_theta of Section 3, eqs. (NumberEight)-(NumberNine).
+ *
+ * Conventions used by every entry point
+ *   - Node (i,j[,k]) has id i + (nx+1)*(j + (ny+1)*k); element (ex,ey[,ez])
+ *     has id ex + nx*(ey + ny*ez) (x fastest).
+ *   - Nodal vectors are node-major with components interleaved: entry
+ *     dim*node + c.  All public vectors are FP64 device pointers.
+ *   - "Gamma" vectors hold the interface dofs, nodes in increasing id order,
+ *     components interleaved: length dim * n_gamma.
+ *   - "Interior" vectors hold the interior dofs packed subdomain by
+ *     subdomain in the library's own local order; edd_get_interior_nodes
+ *     gives that order.
+ *   - Every call is asynchronous on the stream given to edd_setup_mesh
+ *     unless it says it synchronises.  A handle is used by one host thread
+ *     at a time.  The caller owns every *_dev buffer and the stream; the
+ *     library owns the handle and all memory it allocates (through the
+ *     allocator given at setup, or hipMalloc when that is NULL) and frees
+ *     it in edd_destroy.
+ *   - Return values: EDD_OK (0), EDD_NOT_CONVERGED (1, results valid), or a
+ *     negative error code; no C++ exception crosses this interface.
+ */
+#ifndef EDD_H
+#define EDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ----------------------------------------------------- */
+#define EDD_OK 0
+#define EDD_NOT_CONVERGED 1
+#define EDD_EINVAL (-1)     /* bad argument (sizes, NaN/Inf, E <= 0, ...)   */
+#define EDD_ENOMEM (-2)     /* device allocation failed                     */
+#define EDD_EHIP (-3)       /* a HIP call failed; see edd_last_hip_error    */
+#define EDD_ESTATE (-4)     /* call out of order (e.g. solve before moduli) */
+#define EDD_ENOTSPD (-5)    /* a pivot of an interior factor was <= 0       */
+#define EDD_EBREAKDOWN (-6) /* Krylov breakdown (p^T S p <= 0, NaN, ...)    */
+
+/* ---- enumerations ----------------------------------------------------- */
+#define EDD_F64 1 /* dtype / factor precision bits */
+#define EDD_F32 2
+
+#define EDD_CLAMP_X0 1 /* clamped faces (u = 0 on the Dirichlet boundary) */
+#define EDD_CLAMP_X1 2
+#define EDD_CLAMP_Y0 4
+#define EDD_CLAMP_Y1 8
+#define EDD_CLAMP_Z0 16
+#define EDD_CLAMP_Z1 32
+
+#define EDD_MODE_F64 0   /* everything in FP64                               */
+#define EDD_MODE_MIXED 1 /* FP64 outer Krylov on K; inner Schur solves with  */
+                         /* FP32 interior factors and an FP32 preconditioner */
+
+#define EDD_PC_IDENTITY 0 /* S~ = I                                           */
+#define EDD_PC_HTHETA 1   /* S~ = Hhat_theta by inverse Lanczos (Section 3)   */
+
+/* stats.flags bits */
+#define EDD_FLAG_TRUE_RES_RESTART 1 /* recursive residual disagreed; restarted */
+#define EDD_FLAG_MIXED_FALLBACK 2   /* mixed path stalled; fell back to FP64   */
+#define EDD_FLAG_PC_DROPPED 4       /* preconditioner output rejected          */
+
+typedef struct edd_problem edd_problem;
+
+/* Device memory callbacks.  alloc returns NULL on failure. */
+typedef struct edd_allocator {
+  void *(*alloc)(void *ctx, size_t bytes);
+  void (*free)(void *ctx, void *ptr);
+  void *ctx;
+} edd_allocator;
+
+/* Geometry of one problem (host memory, read during the call only). */
+typedef struct edd_mesh_desc {
+  int dim;              /* 2 or 3                                            */
+  int nel[3];           /* elements per axis; nel[2] ignored when dim == 2   */
+  int ncuts[3];         /* entries of cuts[a] (subdomain blocks + 1)         */
+  const int *cuts[3];   /* increasing cut positions, cuts[a][0] = 0 and      */
+                        /* cuts[a][ncuts[a]-1] = nel[a]; blocks may differ   */
+  double nu;            /* Poisson ratio, -1 < nu < 1/2 (Section 1)          */
+  int clamp_faces;      /* EDD_CLAMP_* bitmask; at least one face            */
+  int factor_precision; /* EDD_F64 and/or EDD_F32: which interior factors    */
+                        /* edd_set_element_moduli builds                     */
+} edd_mesh_desc;
+
+typedef struct edd_solve_opts {
+  double tol;         /* stop when ||f - K u||_2 <= tol * ||f||_2 (free dofs) */
+  int maxit;          /* max interface iterations (per inner solve if mixed)  */
+  int precision;      /* EDD_MODE_F64 or EDD_MODE_MIXED                       */
+  int precond;        /* EDD_PC_IDENTITY or EDD_PC_HTHETA                     */
+  double theta;       /* H_theta index in [0,1]; < 0 picks the default for   */
+                      /* the number of subdomains (0.5 at 4, 0.6 at 16,      */
+                      /* 0.7 at 64, 0.75 from 256, log-linear between)       */
+  int lanczos_kmax;   /* max inverse-Lanczos steps per application           */
+  double lanczos_tol; /* relative change that stops Lanczos early            */
+  double inner_tol;   /* relative tolerance of the skeleton-Laplacian PCG    */
+  int inner_maxit;    /* max iterations of that PCG                          */
+  int use_initial_guess; /* u_dev holds an initial guess on entry             */
+  int outer_maxit;    /* mixed mode: max FP64 outer iterations               */
+  double mixed_inner_tol; /* mixed mode: interface tolerance of inner solves  */
+  int flexible_window; /* directions kept by the flexible Krylov (0 = all,   */
+                       /* capped at 256; 1 = short recurrence)               */
+} edd_solve_opts;
+
+typedef struct edd_solve_stats {
+  int status;
+  int iterations;           /* interface Krylov iterations (all inner solves) */
+  int outer_iterations;     /* FP64 outer iterations (mixed mode), else 0     */
+  int precond_applications;
+  int lanczos_steps;        /* total inverse-Lanczos steps                    */
+  int inner_iterations;     /* total skeleton-Laplacian PCG iterations        */
+  int flags;                /* EDD_FLAG_* bits                                */
+  double rel_residual;      /* final ||f - K u|| / ||f|| from an FP64 K apply */
+  double compliance;        /* f^T u (eq. (NumberTen))                        */
+  double t_total_ms;        /* wall time of the call                          */
+  double t_krylov_ms;       /* interface iteration part                       */
+} edd_solve_stats;
+
+typedef struct edd_info {
+  int dim, n_sub;
+  int64_t n_nodes, ndof, n_el;
+  int64_t n_gamma;          /* interface nodes                                */
+  int64_t n_interior_dofs;  /* length of interior vectors                     */
+  int64_t factor_entries;   /* stored band entries over all subdomains        */
+  int max_band;             /* largest half bandwidth                         */
+  int max_sub_dofs;         /* largest subdomain interior size                */
+  int64_t skeleton_faces;   /* face blocks of the interface preconditioner    */
+  int face_classes;         /* distinct face-block shapes                     */
+  double theta_default;
+} edd_info;
+
+/* Fill *o with the defaults: tol 1e-8, maxit 2000, FP64, Hhat_theta with the
+ * default theta, kmax 20, lanczos_tol 1e-2, inner_tol 1e-3 (Section 4),
+ * inner_maxit 50, no initial guess, outer_maxit 20, mixed_inner_tol 1e-3,
+ * flexible_window 0. */
+void edd_default_opts(edd_solve_opts *o);
+
+/* Build a problem handle from the grid, the subdomain cuts, nu and the
+ * clamped faces (Section 1: nodes shared by two or more subdomain closures
+ * form Gamma, clamped nodes are removed, all others are interior to one
+ * subdomain).  Does the host-side bookkeeping, uploads the maps and builds
+ * the geometry-only parts of the interface preconditioner.  hip_stream is
+ * a hipStream_t (NULL = default stream).  On success *out owns all library
+ * memory.  Synchronises. */
+int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
+                   void *hip_stream, edd_problem **out);
+
+/* Set the element moduli E_e (n_el values on the device, element order as
+ * above; dtype EDD_F64 or EDD_F32): K(E) = sum_e E_e K0_e, the linear
+ * dependence of eq. (NumberTen).  Assembles the interior blocks K_{I_i I_i}
+ * and factors them (band Cholesky) in the precision(s) chosen at setup.
+ * Returns EDD_EINVAL if any E_e is not finite and positive, EDD_ENOTSPD if
+ * a pivot is not positive.  Synchronises (to report those errors). */
+int edd_set_element_moduli(edd_problem *p, const void *E_dev, int dtype);
+
+/* y = K(E) u over all dofs (Section 2, eq. (NumberFour)).  Clamped entries
+ * of u are ignored (treated as 0) and clamped entries of y are set to 0.
+ * u_dev and y_dev must not overlap.  Requires moduli. */
+int edd_apply_K(edd_problem *p, const double *u_dev, double *y_dev);
+
+/* Solve K u = f on the free dofs by the three steps of eq. (3MatSplit):
+ * condensation, preconditioned Krylov on S u_G = g, back-substitution.
+ * u_dev receives the full-length solution (0 on clamped dofs); on entry it
+ * is the initial guess if o->use_initial_guess.  s may be NULL.
+ * Synchronises.  Returns EDD_NOT_CONVERGED (u valid, best iterate) when
+ * the tolerance is not met within the iteration limits. */
+int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
+                        const edd_solve_opts *o, edd_solve_stats *s);
+
+/* ---- parts of the path, exposed for checking and for composition ------ */
+
+/* x = K_II^{-1} b on interior vectors (eq. (3MatSplit2), first and third
+ * lines), with the factor of precision EDD_F64 or EDD_F32.  b and x may be
+ * the same buffer. */
+int edd_solve_interior(edd_problem *p, const double *b_dev, double *x_dev,
+                       int precision);
+
+/* y = S v on Gamma vectors, S = K_GG - K_GI K_II^{-1} K_IG (Section 2),
+ * with the interior factor of the given precision. */
+int edd_apply_S(edd_problem *p, const double *v_dev, double *y_dev,
+                int precision);
+
+/* z = S~^{-1} r on Gamma vectors for the preconditioner chosen in *o
+ * (Section 3).  Synchronises when the preconditioner is Hhat_theta. */
+int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
+                      const edd_solve_opts *o);
+
+/* Sizes of the problem. */
+int edd_get_info(edd_problem *p, edd_info *info);
+
+/* Host copies of the node ids behind Gamma vectors (n_gamma entries) and
+ * behind interior vectors (n_interior_dofs / dim entries, one per node). */
+int edd_get_gamma_nodes(edd_problem *p, int32_t *nodes_host);
+int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host);
+
+/* Release everything owned by the handle (NULL is accepted).  Synchronises. */
+int edd_destroy(edd_problem *p);
+
+/* Static description of a status code. */
+const char *edd_strerror(int code);
+
+/* The last hipError_t recorded on the handle (0 when none). */
+int edd_last_hip_error(edd_problem *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EDD_H */

@@ -1,0 +1,645 @@
+// C ABI entry points and the interface-solve driver.
+//
+// The solve follows eq. (3MatSplit) of the paper:
+//   1. condensation   g = f_G - K_GI K_II^{-1} f_I
+//   2. interface      S u_G = g by a flexible preconditioned CG
+//   3. back-subst.    u_I = K_II^{-1} (f_I - K_IG u_G)
+// where S v = K_GG v - K_GI K_II^{-1} K_IG v is applied as (K x)_G with
+// x = (-K_II^{-1} (K [0; v])_I, v): two matrix-free element sweeps and one
+// batched interior solve.  The stopping test uses ||r_G|| <= tol ||f||,
+// which equals the full residual when the interior solves are exact; the
+// final FP64 residual ||f - K u|| is recomputed with the element kernel and
+// the iteration resumes if it is above the tolerance.
+//
+// Mixed mode (the inexact right preconditioner of Section 3): an FP64
+// flexible CG on the full system K u = f whose preconditioner is the whole
+// interface solve above run with FP32 interior factors and a loose
+// interface tolerance.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+using namespace edd;
+
+namespace edd {
+
+// scalar slots in p->scal_d
+enum : int {
+  S_RR = 0,
+  S_FF = 1,
+  S_PQCUR = 2,
+  S_PR = 3,
+  S_RES = 4,  // 4, 5: residual norms
+  S_CMP = 6,  // compliance
+  S_BAD = 7,
+  S_C_BASE = 16,
+  S_PQ_BASE = 16 + 256,
+  S_PC_BASE = 16 + 512,
+  S_TOTAL = 2048
+};
+
+void *dev_alloc(edd_problem *p, size_t bytes) {
+  bytes = ((bytes ? bytes : 8) + 255) & ~(size_t)255;
+  void *ptr = nullptr;
+  if (p->alloc_fn) {
+    ptr = p->alloc_fn(p->alloc_ctx, bytes);
+  } else if (hipMalloc(&ptr, bytes) != hipSuccess) {
+    ptr = nullptr;
+  }
+  if (ptr) p->allocations.push_back(ptr);
+  return ptr;
+}
+
+int check_hip(edd_problem *p, hipError_t e) {
+  if (e != hipSuccess) {
+    p->last_hip_error = (int)e;
+    return EDD_EHIP;
+  }
+  return EDD_OK;
+}
+
+int read_scalars(edd_problem *p, int first, int count) {
+  hipError_t e = hipMemcpyAsync(p->scal_h + first, p->scal_d + first,
+                                sizeof(double) * count, hipMemcpyDeviceToHost,
+                                p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  return check_hip(p, e);
+}
+
+int sync_check(edd_problem *p) {
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  return check_hip(p, e);
+}
+
+// y = S v on interface vectors
+void apply_S(edd_problem *p, const double *v, double *y, int prec) {
+  double *t = p->w_I[2];
+  launch_apply_mapped(p, p->inode_d, p->n_inodes, nullptr, 0.0, v, 1.0, nullptr,
+                      1.0, t);
+  launch_band_solve(p, prec, t, t);
+  launch_apply_mapped(p, p->gnode_d, p->n_gamma, t, -1.0, v, 1.0, nullptr, 1.0, y);
+}
+
+static int ensure_window(edd_problem *p, int cap) {
+  if (cap <= p->win_cap) return EDD_OK;
+  const size_t nG = (size_t)p->n_gamma * p->g.dim;
+  double *P = (double *)dev_alloc(p, sizeof(double) * nG * cap);
+  double *Q = (double *)dev_alloc(p, sizeof(double) * nG * cap);
+  if (!P || !Q) return EDD_ENOMEM;
+  p->winP_d = P;
+  p->winQ_d = Q;
+  p->win_cap = cap;
+  return EDD_OK;
+}
+
+// Orthogonalise z against the previous m directions of a ring buffer
+// (capacity cap, newest at slot (k-1) % cap) and write the result to out.
+static void window_orthogonalise(edd_problem *p, int64_t n, double *ringP,
+                                 double *ringQ, int cap, int k, int m,
+                                 const double *z, double *out, int cbase,
+                                 int dbase) {
+  if (m <= 0) {
+    if (out != z) launch_copy(p, n, z, out);
+    return;
+  }
+  const int first = ((k - m) % cap + cap) % cap;
+  int segs[2][2];
+  int ns = 0;
+  if (first + m <= cap) {
+    segs[ns][0] = first; segs[ns][1] = m; ++ns;
+  } else {
+    segs[ns][0] = first; segs[ns][1] = cap - first; ++ns;
+    segs[ns][0] = 0; segs[ns][1] = m - (cap - first); ++ns;
+  }
+  for (int s = 0; s < ns; ++s)
+    launch_window_dots(p, n, segs[s][1], ringQ + (int64_t)segs[s][0] * n, z,
+                       cbase + segs[s][0]);
+  const double *src = z;
+  for (int s = 0; s < ns; ++s) {
+    launch_window_combine(p, n, segs[s][1], ringP + (int64_t)segs[s][0] * n,
+                          cbase + segs[s][0], dbase + segs[s][0], src, out);
+    src = out;
+  }
+}
+
+// Interface solve of K u = f (eq. (3MatSplit)) with interior factors of
+// precision prec.  Stops when ||r_G|| <= tol_abs.  Returns EDD_OK,
+// EDD_NOT_CONVERGED or an error; *iters receives the interface iterations.
+static int schur_solve_core(edd_problem *p, const double *f, double *u, int prec,
+                            double tol_abs, bool use_guess,
+                            const edd_solve_opts *o, edd_solve_stats *st,
+                            int maxit, int window, int *iters) {
+  const int D = p->g.dim;
+  const int64_t nG = p->n_gamma * D;
+  double *x = p->w_G[0], *r = p->w_G[1], *z = p->w_G[2], *g = p->w_G[3],
+         *tmp = p->w_G[4];
+  *iters = 0;
+  // condensation
+  double *wI = p->w_I[0];
+  launch_gather(p, p->inode_d, p->n_inodes, f, wI);
+  launch_band_solve(p, prec, wI, wI);
+  launch_apply_mapped(p, p->gnode_d, p->n_gamma, wI, 1.0, nullptr, 0.0, f, -1.0, g);
+  if (use_guess) {
+    launch_gather(p, p->gnode_d, p->n_gamma, u, x);
+    apply_S(p, x, tmp, prec);
+    launch_copy(p, nG, g, r);
+    launch_axpby(p, nG, -1.0, tmp, 1.0, r);
+  } else {
+    launch_fill(p, nG, 0.0, x);
+    launch_copy(p, nG, g, r);
+  }
+  {
+    const double *a[1] = {r}, *b[1] = {r};
+    launch_dots(p, nG, 1, a, b, S_RR);
+  }
+  int rc = read_scalars(p, S_RR, 1);
+  if (rc) return rc;
+  double rr = p->scal_h[S_RR];
+  if (!std::isfinite(rr)) return EDD_EINVAL;
+  const bool pc_identity = o->precond == EDD_PC_IDENTITY;
+  const int cap = std::max(1, std::min(window, 256));
+  rc = ensure_window(p, cap);
+  if (rc) return rc;
+  int status = EDD_OK;
+  int k = 0;
+  while (std::sqrt(rr) > tol_abs) {
+    if (k >= maxit) { status = EDD_NOT_CONVERGED; break; }
+    const double *zp = r;
+    if (!pc_identity) {
+      rc = precond_apply(p, r, z, o, st, prec == EDD_F32);
+      if (rc) return rc;
+      zp = z;
+    }
+    const int slot = k % cap;
+    double *Pk = p->winP_d + (int64_t)slot * nG;
+    double *Qk = p->winQ_d + (int64_t)slot * nG;
+    const int m = std::min(k, cap);
+    window_orthogonalise(p, nG, p->winP_d, p->winQ_d, cap, k, m, zp, Pk,
+                         S_C_BASE, S_PQ_BASE);
+    apply_S(p, Pk, Qk, prec);
+    {
+      const double *a[2] = {Pk, Pk}, *b[2] = {Qk, r};
+      launch_dots(p, nG, 2, a, b, S_PQCUR);
+    }
+    launch_cg_update(p, nG, S_PR, S_PQCUR, x, Pk, r, Qk, S_RR, S_PQ_BASE + slot);
+    rc = read_scalars(p, S_RR, 4);
+    if (rc) return rc;
+    ++k;
+    rr = p->scal_h[S_RR];
+    if (!(p->scal_h[S_PQCUR] > 0.0) || !std::isfinite(rr)) {
+      status = EDD_EBREAKDOWN;
+      break;
+    }
+  }
+  *iters = k;
+  if (status == EDD_EBREAKDOWN) return status;
+  // back-substitution
+  double *t = p->w_I[1];
+  launch_apply_mapped(p, p->inode_d, p->n_inodes, nullptr, 0.0, x, 1.0, f, -1.0, t);
+  launch_band_solve(p, prec, t, t);
+  launch_scatter_solution(p, t, x, u);
+  return status;
+}
+
+static int true_residual(edd_problem *p, const double *f, const double *u,
+                         double *rel) {
+  launch_apply_full(p, u, p->w_full[0]);
+  launch_residual_norms(p, f, p->w_full[0], S_RES);
+  int rc = read_scalars(p, S_RES, 2);
+  if (rc) return rc;
+  const double rr = p->scal_h[S_RES], ff = p->scal_h[S_RES + 1];
+  *rel = ff > 0 ? std::sqrt(rr / ff) : 0.0;
+  return EDD_OK;
+}
+
+static int norm_f(edd_problem *p, const double *f, double *nf) {
+  launch_residual_norms(p, f, p->w_full[1], S_RES);  // w_full[1] holds zeros
+  int rc = read_scalars(p, S_RES, 2);
+  if (rc) return rc;
+  *nf = std::sqrt(p->scal_h[S_RES + 1]);
+  return EDD_OK;
+}
+
+static int solve_plain(edd_problem *p, const double *f, double *u,
+                       const edd_solve_opts *o, edd_solve_stats *st, double nf) {
+  const int window = o->flexible_window > 0
+                         ? o->flexible_window
+                         : (o->precond == EDD_PC_IDENTITY ? 1 : 256);
+  double tol_abs = o->tol * nf;
+  bool guess = o->use_initial_guess != 0;
+  int status = EDD_OK;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    int its = 0;
+    status = schur_solve_core(p, f, u, EDD_F64, tol_abs, guess, o, st,
+                              o->maxit - st->iterations, window, &its);
+    st->iterations += its;
+    if (status < 0) return status;
+    double rel = 0.0;
+    int rc = true_residual(p, f, u, &rel);
+    if (rc) return rc;
+    st->rel_residual = rel;
+    if (rel <= o->tol || status == EDD_NOT_CONVERGED) break;
+    // recursive residual drifted from the true one: resume from u
+    st->flags |= EDD_FLAG_TRUE_RES_RESTART;
+    tol_abs *= 0.5 * o->tol / rel;
+    guess = true;
+    status = EDD_NOT_CONVERGED;
+  }
+  return status;
+}
+
+struct OuterBuffers {
+  double *r, *z, *P, *Q;
+  int cap;
+};
+
+static int ensure_outer(edd_problem *p, int cap, OuterBuffers *ob) {
+  const size_t nd = (size_t)p->ndof;
+  const size_t need = nd * (2 + 2 * (size_t)cap);
+  if (p->outer_len < need) {
+    double *buf = (double *)dev_alloc(p, sizeof(double) * need);
+    if (!buf) return EDD_ENOMEM;
+    p->outer_d = buf;
+    p->outer_len = need;
+  }
+  ob->r = p->outer_d;
+  ob->z = p->outer_d + nd;
+  ob->P = p->outer_d + 2 * nd;
+  ob->Q = p->outer_d + 2 * nd + nd * cap;
+  ob->cap = cap;
+  return EDD_OK;
+}
+
+static int solve_mixed(edd_problem *p, const double *f, double *u,
+                       const edd_solve_opts *o, edd_solve_stats *st, double nf) {
+  const int64_t n = p->ndof;
+  const int cap = std::max(1, std::min(o->outer_maxit, 64));
+  OuterBuffers ob{};
+  int rc = ensure_outer(p, cap, &ob);
+  if (rc) return rc;
+  const int inner_window = o->flexible_window > 0
+                               ? o->flexible_window
+                               : (o->precond == EDD_PC_IDENTITY ? 1 : 256);
+  // r = f - K u
+  if (o->use_initial_guess) {
+    launch_apply_full(p, u, p->w_full[0]);
+    launch_copy(p, n, f, ob.r);
+    launch_axpby(p, n, -1.0, p->w_full[0], 1.0, ob.r);
+  } else {
+    launch_fill(p, n, 0.0, u);
+    launch_copy(p, n, f, ob.r);
+  }
+  launch_mask_dirichlet(p, ob.r);
+  const double tol_abs = o->tol * nf;
+  double rnorm = 0.0;
+  {
+    const double *a[1] = {ob.r}, *b[1] = {ob.r};
+    launch_dots(p, n, 1, a, b, S_RR);
+    rc = read_scalars(p, S_RR, 1);
+    if (rc) return rc;
+    rnorm = std::sqrt(p->scal_h[S_RR]);
+  }
+  int k = 0;
+  int status = EDD_OK;
+  double prev = rnorm;
+  int stall = 0;
+  while (rnorm > tol_abs) {
+    if (k >= o->outer_maxit) { status = EDD_NOT_CONVERGED; break; }
+    int its = 0;
+    // inner interface solve of K z = r in reduced precision
+    int irc = schur_solve_core(p, ob.r, ob.z, EDD_F32, o->mixed_inner_tol * rnorm,
+                               false, o, st, o->maxit, inner_window, &its);
+    st->iterations += its;
+    if (irc < 0 && irc != EDD_EBREAKDOWN) return irc;
+    const int slot = k % cap;
+    double *Pk = ob.P + (int64_t)slot * n;
+    double *Qk = ob.Q + (int64_t)slot * n;
+    window_orthogonalise(p, n, ob.P, ob.Q, cap, k, std::min(k, cap), ob.z, Pk,
+                         S_C_BASE, S_PQ_BASE);
+    launch_apply_full(p, Pk, Qk);
+    {
+      const double *a[2] = {Pk, Pk}, *b[2] = {Qk, ob.r};
+      launch_dots(p, n, 2, a, b, S_PQCUR);
+    }
+    launch_cg_update(p, n, S_PR, S_PQCUR, u, Pk, ob.r, Qk, S_RR, S_PQ_BASE + slot);
+    rc = read_scalars(p, S_RR, 4);
+    if (rc) return rc;
+    ++k;
+    rnorm = std::sqrt(p->scal_h[S_RR]);
+    if (!(p->scal_h[S_PQCUR] > 0.0) || !std::isfinite(rnorm)) {
+      status = EDD_EBREAKDOWN;
+      break;
+    }
+    stall = (rnorm > 0.5 * prev) ? stall + 1 : 0;
+    prev = rnorm;
+    if (stall >= 2) { status = EDD_NOT_CONVERGED; break; }
+  }
+  st->outer_iterations = k;
+  double rel = 0.0;
+  rc = true_residual(p, f, u, &rel);
+  if (rc) return rc;
+  st->rel_residual = rel;
+  if (rel > o->tol) {
+    // the reduced-precision path did not reach the tolerance: finish with
+    // the FP64 interface solve started from the current iterate
+    st->flags |= EDD_FLAG_MIXED_FALLBACK;
+    edd_solve_opts o2 = *o;
+    o2.use_initial_guess = 1;
+    return solve_plain(p, f, u, &o2, st, nf);
+  }
+  (void)status;
+  return EDD_OK;
+}
+
+}  // namespace edd
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void edd_default_opts(edd_solve_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->maxit = 2000;
+  o->precision = EDD_MODE_F64;
+  o->precond = EDD_PC_HTHETA;
+  o->theta = -1.0;
+  o->lanczos_kmax = 20;
+  o->lanczos_tol = 1e-2;
+  o->inner_tol = 1e-3;
+  o->inner_maxit = 50;
+  o->use_initial_guess = 0;
+  o->outer_maxit = 20;
+  o->mixed_inner_tol = 1e-3;
+  o->flexible_window = 0;
+}
+
+const char *edd_strerror(int code) {
+  switch (code) {
+    case EDD_OK: return "ok";
+    case EDD_NOT_CONVERGED: return "tolerance not reached within the iteration limit";
+    case EDD_EINVAL: return "invalid argument";
+    case EDD_ENOMEM: return "device allocation failed";
+    case EDD_EHIP: return "HIP runtime error";
+    case EDD_ESTATE: return "call out of order (element moduli not set?)";
+    case EDD_ENOTSPD: return "interior block not positive definite";
+    case EDD_EBREAKDOWN: return "Krylov breakdown";
+    default: return "unknown status";
+  }
+}
+
+int edd_last_hip_error(edd_problem *p) { return p ? p->last_hip_error : 0; }
+
+int edd_destroy(edd_problem *p) {
+  if (!p) return EDD_OK;
+  hipStreamSynchronize(p->stream);
+  for (void *ptr : p->allocations) {
+    if (p->free_fn) p->free_fn(p->alloc_ctx, ptr);
+    else hipFree(ptr);
+  }
+  if (p->scal_h) hipHostFree(p->scal_h);
+  delete p;
+  return EDD_OK;
+}
+
+static int validate_desc(const edd_mesh_desc *d) {
+  if (!d || (d->dim != 2 && d->dim != 3)) return EDD_EINVAL;
+  if (!(d->nu > -1.0 && d->nu < 0.5)) return EDD_EINVAL;
+  if ((d->clamp_faces & ((1 << (2 * d->dim)) - 1)) == 0) return EDD_EINVAL;
+  if (!(d->factor_precision & (EDD_F64 | EDD_F32))) return EDD_EINVAL;
+  int64_t nodes = 1;
+  for (int a = 0; a < d->dim; ++a) {
+    if (d->nel[a] < 1 || d->nel[a] > (1 << 20)) return EDD_EINVAL;
+    if (d->ncuts[a] < 2 || !d->cuts[a]) return EDD_EINVAL;
+    if (d->cuts[a][0] != 0 || d->cuts[a][d->ncuts[a] - 1] != d->nel[a]) return EDD_EINVAL;
+    for (int c = 1; c < d->ncuts[a]; ++c)
+      if (d->cuts[a][c] <= d->cuts[a][c - 1]) return EDD_EINVAL;
+    nodes *= d->nel[a] + 1;
+  }
+  if (nodes * d->dim >= ((int64_t)1 << 31)) return EDD_EINVAL;
+  return EDD_OK;
+}
+
+#define EDD_TRY_ALLOC(ptr, type, count)                                      \
+  do {                                                                       \
+    ptr = (type *)edd::dev_alloc(p, sizeof(type) * (size_t)(count));         \
+    if (!ptr) { edd_destroy(p); return EDD_ENOMEM; }                         \
+  } while (0)
+
+int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
+                   void *hip_stream, edd_problem **out) {
+  if (!out) return EDD_EINVAL;
+  *out = nullptr;
+  int rc = validate_desc(d);
+  if (rc) return rc;
+  edd_problem *p = new (std::nothrow) edd_problem();
+  if (!p) return EDD_ENOMEM;
+  p->stream = (hipStream_t)hip_stream;
+  if (a && a->alloc && a->free) {
+    p->alloc_fn = a->alloc;
+    p->free_fn = a->free;
+    p->alloc_ctx = a->ctx;
+  }
+  p->factor_precision = d->factor_precision;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return EDD_EHIP; }
+  rc = build_geometry(p, d);
+  if (rc) { delete p; return rc; }
+  int lds = 0;
+  hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  p->lds_limit = lds > 0 ? (size_t)lds : 65536;
+  if (p->max_kd + 32 > 2048 ||
+      band_solve_lds_bytes(p, EDD_F64) > p->lds_limit) {
+    delete p;
+    return EDD_EINVAL;  // subdomains too large for one workgroup
+  }
+  const int D = p->g.dim;
+  EDD_TRY_ALLOC(p->K0_d, double, 24 * 24);
+  EDD_TRY_ALLOC(p->nmap_d, int, p->n_nodes);
+  EDD_TRY_ALLOC(p->inode_d, int, std::max<int64_t>(1, p->n_inodes));
+  EDD_TRY_ALLOC(p->gnode_d, int, std::max<int64_t>(1, p->n_gamma));
+  EDD_TRY_ALLOC(p->subs_d, SubDesc, p->n_sub);
+  EDD_TRY_ALLOC(p->order_d, int, p->n_sub);
+  EDD_TRY_ALLOC(p->info_d, int, p->n_sub);
+  EDD_TRY_ALLOC(p->E_d, double, p->n_el);
+  EDD_TRY_ALLOC(p->fac64_d, double, std::max<int64_t>(1, p->fac_entries));
+  if (p->factor_precision & EDD_F32)
+    EDD_TRY_ALLOC(p->fac32_d, float, std::max<int64_t>(1, p->fac_entries));
+  for (int i = 0; i < 3; ++i) EDD_TRY_ALLOC(p->w_I[i], double, std::max<int64_t>(1, p->n_idofs));
+  for (int i = 0; i < 8; ++i) EDD_TRY_ALLOC(p->w_G[i], double, std::max<int64_t>(1, p->n_gamma * D));
+  for (int i = 0; i < 2; ++i) EDD_TRY_ALLOC(p->w_full[i], double, p->ndof);
+  p->partials_len = 65536 + 8192;
+  EDD_TRY_ALLOC(p->partials_d, double, p->partials_len);
+  EDD_TRY_ALLOC(p->scal_d, double, S_TOTAL);
+  if (hipHostMalloc((void **)&p->scal_h, sizeof(double) * S_TOTAL) != hipSuccess) {
+    p->scal_h = nullptr;
+    edd_destroy(p);
+    return EDD_ENOMEM;
+  }
+  std::memset(p->scal_h, 0, sizeof(double) * S_TOTAL);
+  hipStream_t s = p->stream;
+  hipError_t e = hipSuccess;
+  auto up = [&](void *dst, const void *src, size_t bytes) {
+    if (e == hipSuccess && bytes)
+      e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  up(p->K0_d, p->K0, sizeof(double) * 24 * 24);
+  up(p->nmap_d, p->nmap_host.data(), sizeof(int) * p->n_nodes);
+  up(p->inode_d, p->inode.data(), sizeof(int) * p->n_inodes);
+  up(p->gnode_d, p->gnode.data(), sizeof(int) * p->n_gamma);
+  up(p->subs_d, p->subs.data(), sizeof(SubDesc) * p->n_sub);
+  up(p->order_d, p->order.data(), sizeof(int) * p->n_sub);
+  up(p->scal_d, p->scal_h, sizeof(double) * S_TOTAL);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) { edd_destroy(p); return EDD_EHIP; }
+  launch_fill(p, p->ndof, 0.0, p->w_full[1]);
+  rc = precond_setup(p);
+  if (rc) { edd_destroy(p); return rc; }
+  rc = sync_check(p);
+  if (rc) { edd_destroy(p); return rc; }
+  *out = p;
+  return EDD_OK;
+}
+
+int edd_set_element_moduli(edd_problem *p, const void *E_dev, int dtype) {
+  if (!p || !E_dev || (dtype != EDD_F64 && dtype != EDD_F32)) return EDD_EINVAL;
+  p->have_moduli = false;
+  launch_convert_moduli(p, E_dev, dtype);
+  launch_check_moduli(p, p->E_d, p->partials_d);
+  launch_reduce(p, 256, 1, 1, S_BAD);
+  int rc = read_scalars(p, S_BAD, 1);
+  if (rc) return rc;
+  if (p->scal_h[S_BAD] != 0.0) return EDD_EINVAL;
+  launch_assemble_band(p);
+  launch_band_cholesky(p);
+  std::vector<int> info(p->n_sub, 0);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(info.data(), p->info_d, sizeof(int) * p->n_sub,
+                       hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return check_hip(p, e);
+  for (int v : info)
+    if (v) return EDD_ENOTSPD;
+  if (p->factor_precision & EDD_F32) launch_band_to_f32(p);
+  rc = sync_check(p);
+  if (rc) return rc;
+  p->have_moduli = true;
+  return EDD_OK;
+}
+
+int edd_apply_K(edd_problem *p, const double *u_dev, double *y_dev) {
+  if (!p || !u_dev || !y_dev) return EDD_EINVAL;
+  if (!p->have_moduli) return EDD_ESTATE;
+  launch_apply_full(p, u_dev, y_dev);
+  return check_hip(p, hipGetLastError());
+}
+
+int edd_solve_interior(edd_problem *p, const double *b_dev, double *x_dev,
+                       int precision) {
+  if (!p || !b_dev || !x_dev) return EDD_EINVAL;
+  if (!p->have_moduli) return EDD_ESTATE;
+  if (precision != EDD_F64 && precision != EDD_F32) return EDD_EINVAL;
+  if (!(p->factor_precision & precision)) return EDD_ESTATE;
+  launch_band_solve(p, precision, b_dev, x_dev);
+  return check_hip(p, hipGetLastError());
+}
+
+int edd_apply_S(edd_problem *p, const double *v_dev, double *y_dev, int precision) {
+  if (!p || !v_dev || !y_dev) return EDD_EINVAL;
+  if (!p->have_moduli) return EDD_ESTATE;
+  if (precision != EDD_F64 && precision != EDD_F32) return EDD_EINVAL;
+  if (!(p->factor_precision & precision)) return EDD_ESTATE;
+  apply_S(p, v_dev, y_dev, precision);
+  return check_hip(p, hipGetLastError());
+}
+
+int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
+                      const edd_solve_opts *o) {
+  if (!p || !r_dev || !z_dev || !o) return EDD_EINVAL;
+  if (o->precond == EDD_PC_IDENTITY) {
+    launch_copy(p, p->n_gamma * p->g.dim, r_dev, z_dev);
+    return check_hip(p, hipGetLastError());
+  }
+  edd_solve_stats st{};
+  int rc = precond_apply(p, r_dev, z_dev, o, &st, o->precision == EDD_MODE_MIXED);
+  if (rc) return rc;
+  return sync_check(p);
+}
+
+int edd_get_info(edd_problem *p, edd_info *info) {
+  if (!p || !info) return EDD_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  info->dim = p->g.dim;
+  info->n_sub = p->n_sub;
+  info->n_nodes = p->n_nodes;
+  info->ndof = p->ndof;
+  info->n_el = p->n_el;
+  info->n_gamma = p->n_gamma;
+  info->n_interior_dofs = p->n_idofs;
+  info->factor_entries = p->fac_entries;
+  info->max_band = p->max_kd;
+  info->max_sub_dofs = p->max_n;
+  info->skeleton_faces = p->n_faces;
+  info->face_classes = p->n_face_classes;
+  info->theta_default = p->theta_default;
+  return EDD_OK;
+}
+
+int edd_get_gamma_nodes(edd_problem *p, int32_t *nodes_host) {
+  if (!p || !nodes_host) return EDD_EINVAL;
+  std::memcpy(nodes_host, p->gnode.data(), sizeof(int32_t) * p->n_gamma);
+  return EDD_OK;
+}
+
+int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host) {
+  if (!p || !nodes_host) return EDD_EINVAL;
+  std::memcpy(nodes_host, p->inode.data(), sizeof(int32_t) * p->n_inodes);
+  return EDD_OK;
+}
+
+int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
+                        const edd_solve_opts *o_in, edd_solve_stats *s_out) {
+  if (!p || !f_dev || !u_dev) return EDD_EINVAL;
+  if (!p->have_moduli) return EDD_ESTATE;
+  edd_solve_opts o;
+  if (o_in) o = *o_in;
+  else edd_default_opts(&o);
+  if (!(o.tol > 0.0) || o.maxit < 1 || o.outer_maxit < 0) return EDD_EINVAL;
+  if (o.precond != EDD_PC_IDENTITY && o.precond != EDD_PC_HTHETA) return EDD_EINVAL;
+  if (o.precision != EDD_MODE_F64 && o.precision != EDD_MODE_MIXED) return EDD_EINVAL;
+  if (o.precision == EDD_MODE_MIXED && !(p->factor_precision & EDD_F32)) return EDD_ESTATE;
+  if (!(p->factor_precision & EDD_F64)) return EDD_ESTATE;
+  edd_solve_stats st{};
+  const auto t0 = std::chrono::steady_clock::now();
+  double nf = 0.0;
+  int rc = norm_f(p, f_dev, &nf);
+  if (rc) return rc;
+  if (!std::isfinite(nf)) return EDD_EINVAL;
+  int status = EDD_OK;
+  if (nf == 0.0) {
+    launch_fill(p, p->ndof, 0.0, u_dev);
+  } else if (o.precision == EDD_MODE_F64) {
+    status = solve_plain(p, f_dev, u_dev, &o, &st, nf);
+  } else {
+    status = solve_mixed(p, f_dev, u_dev, &o, &st, nf);
+  }
+  if (status >= 0) {
+    const double *a[1] = {f_dev}, *b[1] = {u_dev};
+    launch_dots(p, p->ndof, 1, a, b, S_CMP);
+    rc = read_scalars(p, S_CMP, 1);
+    if (rc) return rc;
+    st.compliance = p->scal_h[S_CMP];
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  st.t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  st.status = status;
+  if (s_out) *s_out = st;
+  return status;
+}
+
+}  // extern "C"

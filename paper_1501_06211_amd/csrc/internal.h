@@ -1,0 +1,206 @@
+// Internal declarations of the edd library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/edd.h"
+
+namespace edd {
+
+// Map value of a node (int32 per global node):
+//   >= 0       packed interior dof of component 0
+//   kDirichlet clamped node
+//   <= -2      interface node, index = -(value) - 2
+constexpr int kDirichlet = -1;
+__host__ __device__ inline int gamma_code(int g) { return -g - 2; }
+__host__ __device__ inline int gamma_index(int code) { return -code - 2; }
+
+// Geometry of the structured grid, passed to kernels by value.
+struct Geom {
+  int dim;
+  int nn[3];   // nodes per axis (1 for unused axes)
+  int nel[3];  // elements per axis (1 for unused axes)
+};
+
+// One subdomain's interior block K_{I_i I_i} in band storage.
+// Interior nodes form the box lo[a] .. lo[a]+len[a]-1 (global node
+// coordinates).  Local node index l = a + na*(b + nb*c) with (a, b, c) the
+// coordinates along the axes ax[0] (fastest), ax[1], ax[2] (slowest);
+// local dof p = dim*l + comp.  The lower Cholesky factor is stored by
+// columns: entry (q, p), 0 <= q-p <= kd, at fac[fac_off + p*(kd+1) + q-p].
+struct SubDesc {
+  int n;       // interior dofs
+  int kd;      // half bandwidth
+  int len[3];  // box length along local axes (fast, mid, slow)
+  int ax[3];   // global axis of each local axis
+  int lo[3];   // box origin, indexed by global axis
+  int pad;
+  int64_t dof_off;  // offset in interior vectors
+  int64_t fac_off;  // offset in band storage (entries)
+};
+
+// Skeleton (interface) data for the H_theta preconditioner.
+struct FaceClass {
+  int m;           // nodes per face of this class
+  int64_t inv_off; // offset of the dense m x m inverse (row-major)
+};
+
+}  // namespace edd
+
+// The handle.  Everything below lives in host memory except the *_d
+// pointers, which are device allocations owned by the handle.
+struct edd_problem {
+  // geometry
+  edd::Geom g{};
+  int clamp = 0;
+  double nu = 0.3;
+  int ncuts[3] = {0, 0, 0};
+  std::vector<int> cuts[3];
+  int n_sub = 0;
+  int64_t n_nodes = 0, ndof = 0, n_el = 0;
+  int64_t n_gamma = 0, n_inodes = 0, n_idofs = 0;
+  int factor_precision = EDD_F64;
+
+  // host bookkeeping
+  std::vector<edd::SubDesc> subs;
+  std::vector<int> order;  // launch order of subdomains (largest first)
+  std::vector<int> inode, gnode, nmap_host;
+  int64_t fac_entries = 0;
+  int max_kd = 0, max_n = 0;
+  double K0[24 * 24];
+  double theta_default = 0.5;
+
+  // skeleton / preconditioner (host side)
+  int64_t sk_nnz = 0;
+  int n_faces = 0, n_face_classes = 0;
+  int64_t face_nodes_total = 0, face_inv_entries = 0;
+  int n_rest = 0;
+
+  // device memory
+  void *alloc_ctx = nullptr;
+  void *(*alloc_fn)(void *, size_t) = nullptr;
+  void (*free_fn)(void *, void *) = nullptr;
+  std::vector<void *> allocations;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  size_t lds_limit = 65536;
+
+  double *K0_d = nullptr;
+  int *nmap_d = nullptr, *inode_d = nullptr, *gnode_d = nullptr;
+  edd::SubDesc *subs_d = nullptr;
+  int *order_d = nullptr;
+  int *info_d = nullptr;     // per-subdomain factorisation status
+  double *E_d = nullptr;     // element moduli (FP64 copy)
+  double *fac64_d = nullptr;
+  float *fac32_d = nullptr;
+  bool have_moduli = false;
+
+  // skeleton operators (CSR of L, lumped mass, face blocks)
+  int *skL_rowptr_d = nullptr, *skL_col_d = nullptr;
+  double *skL_val_d = nullptr, *skM_d = nullptr, *skLdiag_d = nullptr;
+  int *face_ptr_d = nullptr;     // start of each face in face_node_d
+  int *face_class_d = nullptr;   // class of each face
+  int *face_node_d = nullptr;    // gamma indices of face nodes (class order)
+  int *rest_d = nullptr;         // gamma indices of cross-point nodes
+  double *face_inv_d = nullptr;  // dense inverses, all classes
+  float *face_inv32_d = nullptr;
+  std::vector<edd::FaceClass> classes;
+  std::vector<int> face_class_h, face_ptr_h;
+  edd::FaceClass *classes_d = nullptr;
+  int max_face_m = 0;
+
+  // work buffers
+  double *w_I[3] = {nullptr, nullptr, nullptr};  // interior vectors
+  double *w_G[8] = {};                           // gamma vectors
+  double *w_full[2] = {nullptr, nullptr};        // full nodal vectors
+  double *partials_d = nullptr;
+  double *scal_d = nullptr;
+  double *scal_h = nullptr;  // pinned
+  size_t partials_len = 0;
+
+  // flexible Krylov window (directions P and S P)
+  int win_cap = 0;
+  double *winP_d = nullptr, *winQ_d = nullptr;
+
+  // preconditioner scratch (Lanczos basis etc.)
+  double *pc_d = nullptr;
+  size_t pc_len = 0;
+  // mixed-mode outer iteration vectors
+  double *outer_d = nullptr;
+  size_t outer_len = 0;
+
+  int last_hip_error = 0;
+};
+
+namespace edd {
+
+// ---- launchers implemented in the .hip files ----------------------------
+// kernels_fe.hip
+void launch_apply_full(edd_problem *p, const double *u, double *y);
+void launch_apply_mapped(edd_problem *p, const int *tgt, int64_t ntgt,
+                         const double *xI, double sI, const double *xG,
+                         double sG, const double *base_global, double sy,
+                         double *out);
+void launch_assemble_band(edd_problem *p);
+void launch_gather(edd_problem *p, const int *nodes, int64_t n,
+                   const double *full, double *packed);
+void launch_scatter_solution(edd_problem *p, const double *uI,
+                             const double *uG, double *u);
+void launch_check_moduli(edd_problem *p, const double *E, double *flag);
+void launch_convert_moduli(edd_problem *p, const void *E, int dtype);
+void launch_mask_dirichlet(edd_problem *p, double *v);
+
+// kernels_band.hip
+void launch_band_cholesky(edd_problem *p);
+void launch_band_to_f32(edd_problem *p);
+void launch_band_solve(edd_problem *p, int precision, const double *b,
+                       double *x);
+
+// kernels_vec.hip
+// dots: out[k] = sum_i a_k[i] * b_k[i] for k < nd (nd <= 4), written to
+// p->scal_d[slot + k].  Deterministic two-stage reduction.
+void launch_dots(edd_problem *p, int64_t n, int nd, const double *const *a,
+                 const double *const *b, int slot);
+// y = a*x + b*y
+void launch_axpby(edd_problem *p, int64_t n, double a, const double *x,
+                  double b, double *y);
+void launch_copy(edd_problem *p, int64_t n, const double *x, double *y);
+void launch_fill(edd_problem *p, int64_t n, double v, double *y);
+// x += alpha*pv; r -= alpha*q with alpha = scal[num]/scal[den]
+// also writes r.r to scal[slot] and copies scal[den] to scal[copy_dst]
+void launch_cg_update(edd_problem *p, int64_t n, int num, int den,
+                      double *x, const double *pv, double *r,
+                      const double *q, int slot, int copy_dst);
+void launch_reduce(edd_problem *p, int nblocks, int stride, int nout, int slot);
+size_t band_solve_lds_bytes(const edd_problem *p, int precision);
+void element_matrix(int dim, double nu, double *K0);
+double default_theta(int nsub);
+int build_geometry(edd_problem *p, const edd_mesh_desc *d);
+// multi-dot against a window of m vectors (stride n): out[j] = <z, W_j>
+void launch_window_dots(edd_problem *p, int64_t n, int m, const double *W,
+                        const double *z, int slot);
+// p = z - sum_j (scal[cslot+j] / scal[dslot+j]) P_j
+void launch_window_combine(edd_problem *p, int64_t n, int m,
+                           const double *P, int cslot, int dslot,
+                           const double *z, double *pv);
+// full-vector residual norms over free dofs: scal[slot] = ||f - y||^2,
+// scal[slot+1] = ||f||^2
+void launch_residual_norms(edd_problem *p, const double *f, const double *y,
+                           int slot);
+
+// preconditioner (kernels_pc.hip)
+int precond_apply(edd_problem *p, const double *r, double *z,
+                  const edd_solve_opts *o, edd_solve_stats *st,
+                  bool low_precision);
+int precond_setup(edd_problem *p);
+
+// helpers (api.hip)
+void *dev_alloc(edd_problem *p, size_t bytes);
+int check_hip(edd_problem *p, hipError_t e);
+int read_scalars(edd_problem *p, int first, int count);
+
+}  // namespace edd

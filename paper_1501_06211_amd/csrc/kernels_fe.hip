@@ -1,0 +1,333 @@
+// Element-level kernels: matrix-free K(E) u, band assembly of the interior
+// blocks K_{I_i I_i}, and the gathers/scatters between nodal, interior and
+// interface vectors.
+//
+// K(E) = sum_e E_e P_e^T K0 P_e (the linear dependence on the element
+// weights of eq. (NumberTen)); K0 is the unit-modulus element matrix of the
+// Q1 quadrilateral (plane stress) or trilinear hexahedron, built on the host
+// by Gauss quadrature.  Products are evaluated node by node (each thread owns
+// the rows of one node and gathers its neighbourhood), so no floating-point
+// atomics are used and results are bitwise reproducible.
+#include "internal.h"
+
+namespace edd {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Local corner numbering: counter-clockwise in the (x, y) face, z = 0 face
+// first for hexahedra.
+__host__ __device__ constexpr int corner_of(int ox, int oy, int oz) {
+  return (oy ? (ox ? 2 : 3) : (ox ? 1 : 0)) + 4 * oz;
+}
+__host__ __device__ constexpr int corner_x(int a) { return (a & 3) == 1 || (a & 3) == 2; }
+__host__ __device__ constexpr int corner_y(int a) { return (a & 3) >= 2; }
+__host__ __device__ constexpr int corner_z(int a) { return a >= 4; }
+
+struct Src {
+  // MODE 0: full nodal vector u (clamped nodes read as 0)
+  // MODE 1: interior/interface packed vectors through the node map
+  const double *u;
+  const double *xI;
+  const double *xG;
+  double sI, sG;
+};
+
+template <int D, int MODE>
+__device__ inline void fetch_node(const Src &s, const int *__restrict__ nmap,
+                                  int node, double *v) {
+  const int code = nmap[node];
+  if (MODE == 0) {
+    if (code == kDirichlet) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) v[c] = 0.0;
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) v[c] = s.u[(int64_t)D * node + c];
+    }
+  } else {
+    if (code >= 0) {
+      if (s.xI) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) v[c] = s.sI * s.xI[code + c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c) v[c] = 0.0;
+      }
+    } else if (code != kDirichlet && s.xG) {
+      const int64_t gi = gamma_index(code);
+#pragma unroll
+      for (int c = 0; c < D; ++c) v[c] = s.sG * s.xG[D * gi + c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) v[c] = 0.0;
+    }
+  }
+}
+
+// y(node) = sum over the elements around the node of E_e * (K0 row block of
+// the node's corner) * (element dofs).
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply(
+    Geom g, const double *__restrict__ K0, const double *__restrict__ E,
+    const int *__restrict__ nmap, const int *__restrict__ tgt, int64_t ntgt,
+    Src src, const double *__restrict__ base, double sy,
+    double *__restrict__ out) {
+  constexpr int NC = (D == 3) ? 8 : 4;
+  constexpr int ND = D * NC;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ntgt) return;
+  const int node = tgt ? tgt[t] : (int)t;
+  const int i = node % g.nn[0];
+  const int rem = node / g.nn[0];
+  const int j = rem % g.nn[1];
+  const int k = rem / g.nn[1];
+  double y[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) y[c] = 0.0;
+
+#pragma unroll
+  for (int sz = 0; sz < (D == 3 ? 2 : 1); ++sz) {
+#pragma unroll
+    for (int sy_ = 0; sy_ < 2; ++sy_) {
+#pragma unroll
+      for (int sx = 0; sx < 2; ++sx) {
+        const int ex = i - 1 + sx, ey = j - 1 + sy_;
+        const int ez = (D == 3) ? k - 1 + sz : 0;
+        if (ex < 0 || ex >= g.nel[0] || ey < 0 || ey >= g.nel[1]) continue;
+        if (D == 3 && (ez < 0 || ez >= g.nel[2])) continue;
+        const int64_t e = ex + (int64_t)g.nel[0] * (ey + (int64_t)g.nel[1] * ez);
+        const double Ee = E[e];
+        const int a = corner_of(1 - sx, 1 - sy_, D == 3 ? 1 - sz : 0);
+        double xe[ND];
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+          const int nb = (ex + corner_x(b)) +
+                         g.nn[0] * ((ey + corner_y(b)) + g.nn[1] * (ez + corner_z(b)));
+          fetch_node<D, MODE>(src, nmap, nb, xe + D * b);
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const double *row = K0 + (a * D + c) * ND;
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < ND; ++m) acc = fma(row[m], xe[m], acc);
+          y[c] = fma(Ee, acc, y[c]);
+        }
+      }
+    }
+  }
+  if (MODE == 0) {
+    const bool dir = nmap[node] == kDirichlet;
+#pragma unroll
+    for (int c = 0; c < D; ++c) out[(int64_t)D * node + c] = dir ? 0.0 : y[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double b0 = base ? base[(int64_t)D * node + c] : 0.0;
+      out[D * t + c] = fma(sy, y[c], b0);
+    }
+  }
+}
+
+// One thread per stored band entry (column p, offset r) of every subdomain:
+// K[q, p] with q = p + r, summed over the elements shared by the two nodes.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_assemble_band(
+    Geom g, const double *__restrict__ K0, const double *__restrict__ E,
+    const SubDesc *__restrict__ subs, double *__restrict__ fac) {
+  constexpr int NC = (D == 3) ? 8 : 4;
+  constexpr int ND = D * NC;
+  const SubDesc s = subs[blockIdx.y];
+  const int ld = s.kd + 1;
+  const int64_t total = (int64_t)s.n * ld;
+  double *band = fac + s.fac_off;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e / ld);
+    const int r = (int)(e - (int64_t)p * ld);
+    const int q = p + r;
+    double val = 0.0;
+    if (q < s.n) {
+      const int l1 = p / D, c1 = p - l1 * D;
+      const int l2 = q / D, c2 = q - l2 * D;
+      int loc1[3], loc2[3];
+      loc1[0] = l1 % s.len[0];
+      loc1[1] = (l1 / s.len[0]) % s.len[1];
+      loc1[2] = l1 / (s.len[0] * s.len[1]);
+      loc2[0] = l2 % s.len[0];
+      loc2[1] = (l2 / s.len[0]) % s.len[1];
+      loc2[2] = l2 / (s.len[0] * s.len[1]);
+      int x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
+      bool near = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (a >= D) continue;
+        const int gax = s.ax[a];
+        x1[gax] = s.lo[gax] + loc1[a];
+        x2[gax] = s.lo[gax] + loc2[a];
+        const int df = loc2[a] - loc1[a];
+        near = near && df >= -1 && df <= 1;
+      }
+      if (near) {
+        // candidate element origins per axis
+        int e0[3], e1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          if (a >= D) { e0[a] = 0; e1[a] = 0; continue; }
+          if (x1[a] == x2[a]) { e0[a] = x1[a] - 1; e1[a] = x1[a]; }
+          else { e0[a] = min(x1[a], x2[a]); e1[a] = e0[a]; }
+          e0[a] = max(e0[a], 0);
+          e1[a] = min(e1[a], g.nel[a] - 1);
+        }
+        for (int ez = e0[2]; ez <= e1[2]; ++ez)
+          for (int ey = e0[1]; ey <= e1[1]; ++ey)
+            for (int ex = e0[0]; ex <= e1[0]; ++ex) {
+              const int a1 = corner_of(x1[0] - ex, x1[1] - ey, D == 3 ? x1[2] - ez : 0);
+              const int a2 = corner_of(x2[0] - ex, x2[1] - ey, D == 3 ? x2[2] - ez : 0);
+              const int64_t el = ex + (int64_t)g.nel[0] * (ey + (int64_t)g.nel[1] * ez);
+              val = fma(E[el], K0[(a2 * D + c2) * ND + a1 * D + c1], val);
+            }
+      }
+    }
+    band[e] = val;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(int dim,
+                                                   const int *__restrict__ nodes,
+                                                   int64_t n,
+                                                   const double *__restrict__ full,
+                                                   double *__restrict__ packed) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * dim) return;
+  const int64_t node = t / dim;
+  const int c = (int)(t - node * dim);
+  packed[t] = full[(int64_t)dim * nodes[node] + c];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_solution(
+    int dim, int64_t n_nodes, const int *__restrict__ nmap,
+    const double *__restrict__ uI, const double *__restrict__ uG,
+    double *__restrict__ u) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n_nodes * dim) return;
+  const int64_t node = t / dim;
+  const int c = (int)(t - node * dim);
+  const int code = nmap[node];
+  double v = 0.0;
+  if (code >= 0) v = uI[code + c];
+  else if (code != kDirichlet) v = uG[(int64_t)dim * gamma_index(code) + c];
+  u[t] = v;
+}
+
+// Per-block count of moduli that are not finite and positive.
+__global__ __launch_bounds__(kBlock) void k_check_moduli(
+    const double *__restrict__ E, int64_t n, double *__restrict__ partials) {
+  __shared__ double red[kBlock / 64];
+  double bad = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const double v = E[t];
+    bad += (v > 0.0 && v <= 1.7e308) ? 0.0 : 1.0;  // NaN fails both
+  }
+  for (int o = 32; o > 0; o >>= 1) bad += __shfl_down(bad, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+    partials[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_f32_to_f64(const float *__restrict__ a,
+                                                       double *__restrict__ b,
+                                                       int64_t n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) b[t] = (double)a[t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_mask_dirichlet(
+    int dim, int64_t n_nodes, const int *__restrict__ nmap, double *__restrict__ v) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n_nodes * dim) return;
+  if (nmap[t / dim] == kDirichlet) v[t] = 0.0;
+}
+
+inline unsigned grid_for(int64_t n) {
+  return (unsigned)((n + kBlock - 1) / kBlock);
+}
+
+}  // namespace
+
+void launch_apply_full(edd_problem *p, const double *u, double *y) {
+  Src s{u, nullptr, nullptr, 0.0, 0.0};
+  const int64_t n = p->n_nodes;
+  if (p->g.dim == 2)
+    k_apply<2, 0><<<grid_for(n), kBlock, 0, p->stream>>>(
+        p->g, p->K0_d, p->E_d, p->nmap_d, nullptr, n, s, nullptr, 1.0, y);
+  else
+    k_apply<3, 0><<<grid_for(n), kBlock, 0, p->stream>>>(
+        p->g, p->K0_d, p->E_d, p->nmap_d, nullptr, n, s, nullptr, 1.0, y);
+}
+
+void launch_apply_mapped(edd_problem *p, const int *tgt, int64_t ntgt,
+                         const double *xI, double sI, const double *xG,
+                         double sG, const double *base_global, double sy,
+                         double *out) {
+  if (ntgt == 0) return;
+  Src s{nullptr, xI, xG, sI, sG};
+  if (p->g.dim == 2)
+    k_apply<2, 1><<<grid_for(ntgt), kBlock, 0, p->stream>>>(
+        p->g, p->K0_d, p->E_d, p->nmap_d, tgt, ntgt, s, base_global, sy, out);
+  else
+    k_apply<3, 1><<<grid_for(ntgt), kBlock, 0, p->stream>>>(
+        p->g, p->K0_d, p->E_d, p->nmap_d, tgt, ntgt, s, base_global, sy, out);
+}
+
+void launch_assemble_band(edd_problem *p) {
+  dim3 grid(256, p->n_sub);
+  if (p->g.dim == 2)
+    k_assemble_band<2><<<grid, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d,
+                                                        p->subs_d, p->fac64_d);
+  else
+    k_assemble_band<3><<<grid, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d,
+                                                        p->subs_d, p->fac64_d);
+}
+
+void launch_gather(edd_problem *p, const int *nodes, int64_t n,
+                   const double *full, double *packed) {
+  const int64_t m = n * p->g.dim;
+  if (m == 0) return;
+  k_gather<<<grid_for(m), kBlock, 0, p->stream>>>(p->g.dim, nodes, n, full, packed);
+}
+
+void launch_scatter_solution(edd_problem *p, const double *uI,
+                             const double *uG, double *u) {
+  const int64_t m = p->n_nodes * p->g.dim;
+  k_scatter_solution<<<grid_for(m), kBlock, 0, p->stream>>>(
+      p->g.dim, p->n_nodes, p->nmap_d, uI, uG, u);
+}
+
+void launch_check_moduli(edd_problem *p, const double *E, double *flag_partials) {
+  k_check_moduli<<<256, kBlock, 0, p->stream>>>(E, p->n_el, flag_partials);
+}
+
+void launch_convert_moduli(edd_problem *p, const void *E, int dtype) {
+  if (dtype == EDD_F64) {
+    hipMemcpyAsync(p->E_d, E, sizeof(double) * p->n_el, hipMemcpyDeviceToDevice,
+                   p->stream);
+  } else {
+    k_f32_to_f64<<<grid_for(p->n_el), kBlock, 0, p->stream>>>(
+        (const float *)E, p->E_d, p->n_el);
+  }
+}
+
+void launch_mask_dirichlet(edd_problem *p, double *v) {
+  const int64_t m = p->n_nodes * p->g.dim;
+  k_mask_dirichlet<<<grid_for(m), kBlock, 0, p->stream>>>(p->g.dim, p->n_nodes,
+                                                          p->nmap_d, v);
+}
+
+}  // namespace edd

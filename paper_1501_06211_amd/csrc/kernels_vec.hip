@@ -1,0 +1,233 @@
+// Vector kernels of the interface Krylov iteration.  Dot products use a
+// deterministic two-stage reduction: each block writes its partial sums,
+// then one block per result sums the partials in a fixed order.  Scalars
+// (alpha, the dots) stay on the device in p->scal_d, so the iteration does
+// not wait on the host between kernels.
+#include "internal.h"
+
+namespace edd {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxBlocks = 1024;
+
+__device__ inline double block_sum(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  }
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+struct DotArgs {
+  const double *a[4];
+  const double *b[4];
+};
+
+template <int ND>
+__global__ __launch_bounds__(kBlock) void k_dots(int64_t n, DotArgs args,
+                                                 double *__restrict__ partials) {
+  __shared__ double red[kBlock / 64];
+  double acc[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[k] = fma(args.a[k][i], args.b[k][i], acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    const double s = block_sum(acc[k], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * ND + k] = s;
+  }
+}
+
+// out[slot + j] = sum_b partials[b*stride + j], one block per j.
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *__restrict__ partials,
+                                                   int nblocks, int stride,
+                                                   double *__restrict__ out) {
+  __shared__ double red[kBlock / 64];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    acc += partials[(int64_t)b * stride + j];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpby(int64_t n, double a,
+                                                  const double *__restrict__ x,
+                                                  double b, double *__restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double v,
+                                                 double *__restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+// x += alpha p, r -= alpha q with alpha = scal[num]/scal[den]; partial
+// sums of r.r for the convergence test; optionally keeps a copy of the
+// denominator (p^T S p) for the window of previous directions.
+__global__ __launch_bounds__(kBlock) void k_cg_update(
+    int64_t n, const double *__restrict__ scal, int num, int den,
+    double *__restrict__ x, const double *__restrict__ pv,
+    double *__restrict__ r, const double *__restrict__ q,
+    double *__restrict__ partials, double *__restrict__ copy_to) {
+  __shared__ double red[kBlock / 64];
+  const double alpha = scal[num] / scal[den];
+  if (copy_to && blockIdx.x == 0 && threadIdx.x == 0) *copy_to = scal[den];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] = fma(alpha, pv[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    acc = fma(ri, ri, acc);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// partials[b*m + j] = sum over the block's range of z[i] * W[j*n + i]
+__global__ __launch_bounds__(kBlock) void k_window_dots(
+    int64_t n, int m, const double *__restrict__ W, const double *__restrict__ z,
+    double *__restrict__ partials) {
+  __shared__ double red[kBlock / 64];
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk;
+  const int64_t hi = min(n, lo + chunk);
+  for (int j = 0; j < m; ++j) {
+    double acc = 0.0;
+    const double *Wj = W + (int64_t)j * n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+      acc = fma(z[i], Wj[i], acc);
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * m + j] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_window_combine(
+    int64_t n, int m, const double *__restrict__ P,
+    const double *__restrict__ scal, int cslot, int dslot,
+    const double *__restrict__ z, double *__restrict__ pv) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = z[i];
+    for (int j = 0; j < m; ++j)
+      v = fma(-(scal[cslot + j] / scal[dslot + j]), P[(int64_t)j * n + i], v);
+    pv[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual_norms(
+    int dim, int64_t n_nodes, const int *__restrict__ nmap,
+    const double *__restrict__ f, const double *__restrict__ y,
+    double *__restrict__ partials) {
+  __shared__ double red[kBlock / 64];
+  double rr = 0.0, ff = 0.0;
+  const int64_t n = n_nodes * dim;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (nmap[i / dim] != kDirichlet) {
+      const double d = f[i] - y[i];
+      rr = fma(d, d, rr);
+      ff = fma(f[i], f[i], ff);
+    }
+  }
+  const double a = block_sum(rr, red);
+  const double b = block_sum(ff, red);
+  if (threadIdx.x == 0) {
+    partials[(int64_t)blockIdx.x * 2] = a;
+    partials[(int64_t)blockIdx.x * 2 + 1] = b;
+  }
+}
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > kMaxBlocks) g = kMaxBlocks;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+void launch_dots(edd_problem *p, int64_t n, int nd, const double *const *a,
+                 const double *const *b, int slot) {
+  DotArgs args{};
+  for (int k = 0; k < nd; ++k) {
+    args.a[k] = a[k];
+    args.b[k] = b[k];
+  }
+  const unsigned g = grid_for(n);
+  switch (nd) {
+    case 1: k_dots<1><<<g, kBlock, 0, p->stream>>>(n, args, p->partials_d); break;
+    case 2: k_dots<2><<<g, kBlock, 0, p->stream>>>(n, args, p->partials_d); break;
+    case 3: k_dots<3><<<g, kBlock, 0, p->stream>>>(n, args, p->partials_d); break;
+    default: k_dots<4><<<g, kBlock, 0, p->stream>>>(n, args, p->partials_d); break;
+  }
+  k_reduce<<<nd, kBlock, 0, p->stream>>>(p->partials_d, (int)g, nd, p->scal_d + slot);
+}
+
+void launch_axpby(edd_problem *p, int64_t n, double a, const double *x,
+                  double b, double *y) {
+  k_axpby<<<grid_for(n), kBlock, 0, p->stream>>>(n, a, x, b, y);
+}
+
+void launch_copy(edd_problem *p, int64_t n, const double *x, double *y) {
+  hipMemcpyAsync(y, x, sizeof(double) * n, hipMemcpyDeviceToDevice, p->stream);
+}
+
+void launch_fill(edd_problem *p, int64_t n, double v, double *y) {
+  k_fill<<<grid_for(n), kBlock, 0, p->stream>>>(n, v, y);
+}
+
+void launch_cg_update(edd_problem *p, int64_t n, int num, int den, double *x,
+                      const double *pv, double *r, const double *q, int slot,
+                      int copy_dst) {
+  const unsigned g = grid_for(n);
+  k_cg_update<<<g, kBlock, 0, p->stream>>>(
+      n, p->scal_d, num, den, x, pv, r, q, p->partials_d,
+      copy_dst >= 0 ? p->scal_d + copy_dst : nullptr);
+  k_reduce<<<1, kBlock, 0, p->stream>>>(p->partials_d, (int)g, 1, p->scal_d + slot);
+}
+
+void launch_window_dots(edd_problem *p, int64_t n, int m, const double *W,
+                        const double *z, int slot) {
+  if (m <= 0) return;
+  unsigned g = grid_for(n);
+  if (g > 256) g = 256;
+  k_window_dots<<<g, kBlock, 0, p->stream>>>(n, m, W, z, p->partials_d);
+  k_reduce<<<m, kBlock, 0, p->stream>>>(p->partials_d, (int)g, m, p->scal_d + slot);
+}
+
+void launch_window_combine(edd_problem *p, int64_t n, int m, const double *P,
+                           int cslot, int dslot, const double *z, double *pv) {
+  k_window_combine<<<grid_for(n), kBlock, 0, p->stream>>>(n, m, P, p->scal_d,
+                                                          cslot, dslot, z, pv);
+}
+
+void launch_residual_norms(edd_problem *p, const double *f, const double *y,
+                           int slot) {
+  const unsigned g = grid_for(p->n_nodes * p->g.dim);
+  k_residual_norms<<<g, kBlock, 0, p->stream>>>(p->g.dim, p->n_nodes, p->nmap_d,
+                                                f, y, p->partials_d);
+  k_reduce<<<2, kBlock, 0, p->stream>>>(p->partials_d, (int)g, 2, p->scal_d + slot);
+}
+
+void launch_reduce(edd_problem *p, int nblocks, int stride, int nout, int slot) {
+  k_reduce<<<nout, kBlock, 0, p->stream>>>(p->partials_d, nblocks, stride,
+                                           p->scal_d + slot);
+}
+
+}  // namespace edd

@@ -1,0 +1,316 @@
+"""ctypes binding of the edd C ABI (include/edd.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch supplies device memory (through the library's allocator callbacks,
+so the caching allocator owns every buffer) and the HIP stream.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libedd.so")
+
+# status codes
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ENOMEM, EHIP, ESTATE, ENOTSPD, EBREAKDOWN = -1, -2, -3, -4, -5, -6
+F64, F32 = 1, 2
+CLAMP_X0, CLAMP_X1, CLAMP_Y0, CLAMP_Y1, CLAMP_Z0, CLAMP_Z1 = 1, 2, 4, 8, 16, 32
+MODE_F64, MODE_MIXED = 0, 1
+PC_IDENTITY, PC_HTHETA = 0, 1
+FLAG_TRUE_RES_RESTART, FLAG_MIXED_FALLBACK, FLAG_PC_DROPPED = 1, 2, 4
+
+EXPORTS = [
+    "edd_default_opts", "edd_setup_mesh", "edd_set_element_moduli",
+    "edd_apply_K", "edd_solve_interface", "edd_solve_interior", "edd_apply_S",
+    "edd_apply_precond", "edd_get_info", "edd_get_gamma_nodes",
+    "edd_get_interior_nodes", "edd_destroy", "edd_strerror",
+    "edd_last_hip_error",
+]
+
+
+class EddError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = lib().edd_strerror(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{what}: {msg} (status {code})")
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("nel", ctypes.c_int * 3),
+        ("ncuts", ctypes.c_int * 3),
+        ("cuts", ctypes.POINTER(ctypes.c_int) * 3),
+        ("nu", ctypes.c_double),
+        ("clamp_faces", ctypes.c_int),
+        ("factor_precision", ctypes.c_int),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("maxit", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("precond", ctypes.c_int),
+        ("theta", ctypes.c_double),
+        ("lanczos_kmax", ctypes.c_int),
+        ("lanczos_tol", ctypes.c_double),
+        ("inner_tol", ctypes.c_double),
+        ("inner_maxit", ctypes.c_int),
+        ("use_initial_guess", ctypes.c_int),
+        ("outer_maxit", ctypes.c_int),
+        ("mixed_inner_tol", ctypes.c_double),
+        ("flexible_window", ctypes.c_int),
+    ]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("iterations", ctypes.c_int),
+        ("outer_iterations", ctypes.c_int),
+        ("precond_applications", ctypes.c_int),
+        ("lanczos_steps", ctypes.c_int),
+        ("inner_iterations", ctypes.c_int),
+        ("flags", ctypes.c_int),
+        ("rel_residual", ctypes.c_double),
+        ("compliance", ctypes.c_double),
+        ("t_total_ms", ctypes.c_double),
+        ("t_krylov_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n_sub", ctypes.c_int),
+        ("n_nodes", ctypes.c_int64), ("ndof", ctypes.c_int64),
+        ("n_el", ctypes.c_int64), ("n_gamma", ctypes.c_int64),
+        ("n_interior_dofs", ctypes.c_int64), ("factor_entries", ctypes.c_int64),
+        ("max_band", ctypes.c_int), ("max_sub_dofs", ctypes.c_int),
+        ("skeleton_faces", ctypes.c_int64), ("face_classes", ctypes.c_int),
+        ("theta_default", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_T), ("free", FREE_T), ("ctx", ctypes.c_void_p)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libedd.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+            "(there is no fallback path)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.edd_default_opts.argtypes = [ctypes.POINTER(SolveOpts)]
+    L.edd_default_opts.restype = None
+    L.edd_setup_mesh.argtypes = [ctypes.POINTER(MeshDesc), ctypes.POINTER(Allocator),
+                                 vp, ctypes.POINTER(vp)]
+    L.edd_set_element_moduli.argtypes = [vp, vp, i32]
+    L.edd_apply_K.argtypes = [vp, vp, vp]
+    L.edd_solve_interface.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                      ctypes.POINTER(SolveStats)]
+    L.edd_solve_interior.argtypes = [vp, vp, vp, i32]
+    L.edd_apply_S.argtypes = [vp, vp, vp, i32]
+    L.edd_apply_precond.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts)]
+    L.edd_get_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.edd_get_gamma_nodes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.edd_get_interior_nodes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.edd_destroy.argtypes = [vp]
+    L.edd_strerror.argtypes = [i32]
+    L.edd_strerror.restype = ctypes.c_char_p
+    L.edd_last_hip_error.argtypes = [vp]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("edd_default_opts", "edd_strerror"):
+            f.restype = i32
+    _LIB = L
+    return L
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().edd_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(f"unknown solve option {k!r}")
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t: torch.Tensor, dtype=torch.float64):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous CUDA {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class _TorchAllocator:
+    """Routes the library's device allocations through torch's caching
+    allocator on the handle's stream."""
+
+    def __init__(self, device, stream):
+        self.device = device
+        self.stream = stream
+
+        def _alloc(ctx, nbytes):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                          self.stream)
+            except Exception:  # pragma: no cover - reported as ENOMEM
+                return None
+
+        def _free(ctx, ptr):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = ALLOC_T(_alloc)
+        self._free = FREE_T(_free)
+        self.struct = Allocator(self._alloc, self._free, None)
+
+
+class Problem:
+    """One decomposed elasticity problem on the current GPU.
+
+    dim, nel, cuts, nu, clamp describe the grid as in include/edd.h;
+    factor_precision selects which interior factors are built (F64, F32 or
+    both).  All vectors are FP64 CUDA tensors in node-major layout.
+    """
+
+    def __init__(self, dim, nel, cuts, nu=0.3, clamp=CLAMP_X0,
+                 factor_precision=F64 | F32, stream=None, torch_allocator=True):
+        L = lib()
+        self.dim = int(dim)
+        self.device = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        d = MeshDesc()
+        d.dim = self.dim
+        self._cut_arrays = []
+        for a in range(3):
+            d.nel[a] = int(nel[a]) if a < dim else 1
+            if a < dim:
+                arr = (ctypes.c_int * len(cuts[a]))(*[int(c) for c in cuts[a]])
+                self._cut_arrays.append(arr)
+                d.cuts[a] = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int))
+                d.ncuts[a] = len(cuts[a])
+        d.nu = float(nu)
+        d.clamp_faces = int(clamp)
+        d.factor_precision = int(factor_precision)
+        self.factor_precision = int(factor_precision)
+        self._alloc = _TorchAllocator(self.device, self.stream) if torch_allocator else None
+        h = ctypes.c_void_p()
+        rc = L.edd_setup_mesh(ctypes.byref(d),
+                              ctypes.byref(self._alloc.struct) if self._alloc else None,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != OK:
+            raise EddError(rc, "edd_setup_mesh")
+        self.h = h
+        info = Info()
+        L.edd_get_info(self.h, ctypes.byref(info))
+        self.info = info.as_dict()
+        self.n_nodes = self.info["n_nodes"]
+        self.ndof = self.info["ndof"]
+        self.n_gamma = self.info["n_gamma"]
+        self.n_interior_dofs = self.info["n_interior_dofs"]
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        return cls(w.dim, w.nel, w.cuts, nu=w.nu, clamp=w.clamp, **kw)
+
+    def _check(self, rc, what):
+        if rc not in (OK, NOT_CONVERGED):
+            raise EddError(rc, what)
+        return rc
+
+    def set_element_moduli(self, E: torch.Tensor):
+        dt = {torch.float64: F64, torch.float32: F32}.get(E.dtype)
+        if dt is None:
+            raise ValueError("moduli must be float64 or float32")
+        _ptr(E, E.dtype)
+        self._E = E
+        self._check(lib().edd_set_element_moduli(self.h, ctypes.c_void_p(E.data_ptr()), dt),
+                    "edd_set_element_moduli")
+
+    def apply_K(self, u: torch.Tensor, out: torch.Tensor | None = None):
+        if out is None:
+            out = torch.empty_like(u)
+        self._check(lib().edd_apply_K(self.h, _ptr(u), _ptr(out)), "edd_apply_K")
+        return out
+
+    def solve(self, f: torch.Tensor, u: torch.Tensor | None = None, **opts):
+        if u is None:
+            u = torch.zeros_like(f)
+            opts.setdefault("use_initial_guess", 0)
+        o = default_opts(**opts)
+        st = SolveStats()
+        rc = lib().edd_solve_interface(self.h, _ptr(f), _ptr(u), ctypes.byref(o),
+                                       ctypes.byref(st))
+        self._check(rc, "edd_solve_interface")
+        return u, st.as_dict()
+
+    def solve_interior(self, b, out=None, precision=F64):
+        if out is None:
+            out = torch.empty_like(b)
+        self._check(lib().edd_solve_interior(self.h, _ptr(b), _ptr(out), precision),
+                    "edd_solve_interior")
+        return out
+
+    def apply_S(self, v, out=None, precision=F64):
+        if out is None:
+            out = torch.empty_like(v)
+        self._check(lib().edd_apply_S(self.h, _ptr(v), _ptr(out), precision),
+                    "edd_apply_S")
+        return out
+
+    def apply_precond(self, r, out=None, **opts):
+        if out is None:
+            out = torch.empty_like(r)
+        o = default_opts(**opts)
+        self._check(lib().edd_apply_precond(self.h, _ptr(r), _ptr(out), ctypes.byref(o)),
+                    "edd_apply_precond")
+        return out
+
+    def gamma_nodes(self):
+        import numpy as np
+        out = np.zeros(self.n_gamma, dtype=np.int32)
+        lib().edd_get_gamma_nodes(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        return out
+
+    def interior_nodes(self):
+        import numpy as np
+        out = np.zeros(self.n_interior_dofs // self.dim, dtype=np.int32)
+        lib().edd_get_interior_nodes(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().edd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
