@@ -134,7 +134,7 @@ typedef struct edd_info {
   int64_t n_nodes, ndof, n_el;
   int64_t n_gamma;          /* interface nodes                                */
   int64_t n_interior_dofs;  /* length of interior vectors                     */
-  int64_t factor_entries;   /* stored band entries over all subdomains        */
+  int64_t factor_entries;   /* band entries of all K_{I_i I_i} (no padding)   */
   int max_band;             /* largest half bandwidth                         */
   int max_sub_dofs;         /* largest subdomain interior size                */
   int64_t skeleton_faces;   /* face blocks of the interface preconditioner    */
@@ -205,6 +205,29 @@ int edd_get_info(edd_problem *p, edd_info *info);
  * behind interior vectors (n_interior_dofs / dim entries, one per node). */
 int edd_get_gamma_nodes(edd_problem *p, int32_t *nodes_host);
 int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host);
+
+/* ---- kernel timing ----------------------------------------------------- */
+#define EDD_KT_BAND_SOLVE 0    /* batched forward+backward substitution    */
+#define EDD_KT_BAND_CHOLESKY 1 /* batched band Cholesky                    */
+#define EDD_KT_APPLY_K 2       /* full matrix-free K apply                 */
+#define EDD_KT_APPLY_MAPPED 3  /* K apply restricted to interior/interface */
+#define EDD_KT_ASSEMBLE 4      /* band assembly of K_II                    */
+#define EDD_KT_PRECOND 5       /* interface preconditioner kernels         */
+#define EDD_KT_LAYOUTS 6       /* solve layouts of the interior factors    */
+#define EDD_KT_COUNT 8
+
+typedef struct edd_kernel_times {
+  int64_t count[EDD_KT_COUNT];   /* launches timed                          */
+  double total_ms[EDD_KT_COUNT]; /* sum of their durations (HIP events on   */
+                                 /* the handle's stream around each launch) */
+} edd_kernel_times;
+
+/* Enable (1) or disable (0) per-launch timing of the kernel families above
+ * and reset the counters.  Timing adds two event records per launch. */
+int edd_set_kernel_timing(edd_problem *p, int enable);
+
+/* Resolve pending events (synchronises) and return the accumulated times. */
+int edd_get_kernel_times(edd_problem *p, edd_kernel_times *t);
 
 /* Release everything owned by the handle (NULL is accepted).  Synchronises. */
 int edd_destroy(edd_problem *p);

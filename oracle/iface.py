@@ -29,6 +29,13 @@ Readings (the defining report is not available):
   nodes shared by exactly the same two subdomains; nodes shared by three or
   more subdomains (cross points, and in 3D the wire-basket edges) are left
   to the diagonal of L.
+
+Extension beyond the paper (its analysis is for one homogeneous material):
+``weighted=True`` multiplies each skeleton element's mass and Laplacian by
+the mean modulus of the two volume elements on either side of it, so the
+interface norm follows the local scale of the Steklov-Poincare operator in
+heterogeneous (SIMP) designs.  With a constant modulus c it is c times the
+unweighted form.
 """
 from __future__ import annotations
 
@@ -73,54 +80,78 @@ def _quad_matrices():
     return Me, Le
 
 
-def skeleton_elements(prob):
-    """Node ids of every skeleton element (edges in 2D, faces in 3D), each
-    listed once, lying on an internal cut line/plane."""
+def skeleton_elements(prob, adjacent=False):
+    """Node ids of every skeleton element (edges in 2D, faces in 3D) lying
+    on an internal cut line/plane, each listed once.  With ``adjacent`` also
+    return the ids of the two volume elements on either side."""
     nn = prob.nnodes_axis
-    out = []
+    out, adj = [], []
     if prob.dim == 2:
+        nx = prob.nel[0]
+
         def nid(i, j):
             return i + nn[0] * j
+
+        def eid(i, j):
+            return i + nx * j
         for c in prob.cuts[0][1:-1]:      # vertical lines x = c
             for j in range(prob.nel[1]):
                 out.append((nid(c, j), nid(c, j + 1)))
+                adj.append((eid(c - 1, j), eid(c, j)))
         for c in prob.cuts[1][1:-1]:      # horizontal lines y = c
             for i in range(prob.nel[0]):
                 out.append((nid(i, c), nid(i + 1, c)))
-        return np.unique(np.array(out, dtype=np.int64).reshape(-1, 2), axis=0)
+                adj.append((eid(i, c - 1), eid(i, c)))
+    else:
+        def nid(i, j, k):
+            return i + nn[0] * (j + nn[1] * k)
 
-    def nid(i, j, k):
-        return i + nn[0] * (j + nn[1] * k)
-    for ax in range(3):
-        a1, a2 = [a for a in range(3) if a != ax]
-        for c in prob.cuts[ax][1:-1]:
-            for p in range(prob.nel[a1]):
-                for q in range(prob.nel[a2]):
-                    quad = []
-                    for (dp, dq) in [(0, 0), (1, 0), (1, 1), (0, 1)]:
-                        ijk = [0, 0, 0]
-                        ijk[ax] = c
-                        ijk[a1] = p + dp
-                        ijk[a2] = q + dq
-                        quad.append(nid(*ijk))
-                    out.append(tuple(quad))
+        def eid(i, j, k):
+            return i + prob.nel[0] * (j + prob.nel[1] * k)
+        for ax in range(3):
+            a1, a2 = [a for a in range(3) if a != ax]
+            for c in prob.cuts[ax][1:-1]:
+                for p in range(prob.nel[a1]):
+                    for q in range(prob.nel[a2]):
+                        quad = []
+                        for (dp, dq) in [(0, 0), (1, 0), (1, 1), (0, 1)]:
+                            ijk = [0, 0, 0]
+                            ijk[ax] = c
+                            ijk[a1] = p + dp
+                            ijk[a2] = q + dq
+                            quad.append(nid(*ijk))
+                        out.append(tuple(quad))
+                        e = [0, 0, 0]
+                        e[a1], e[a2] = p, q
+                        e0, e1 = list(e), list(e)
+                        e0[ax], e1[ax] = c - 1, c
+                        adj.append((eid(*e0), eid(*e1)))
     arr = np.array(out, dtype=np.int64)
-    # faces on two different planes never coincide; drop exact duplicates
-    _, idx = np.unique(np.sort(arr, axis=1), axis=0, return_index=True)
-    return arr[np.sort(idx)]
+    adj = np.array(adj, dtype=np.int64)
+    # an element lies on one cut line/plane only; no duplicates to drop
+    if adjacent:
+        return arr, adj
+    return arr
 
 
-def skeleton_matrices(prob, lumped=False):
-    """(M, L, gamma node ids) on the free skeleton nodes, sparse CSR."""
-    els = skeleton_elements(prob)
+def skeleton_matrices(prob, lumped=False, weighted=False, E=None):
+    """(M, L, gamma node ids) on the free skeleton nodes, sparse CSR.
+    ``weighted`` scales each skeleton element by the mean modulus of its two
+    neighbouring volume elements (see the module docstring)."""
+    els, adj = skeleton_elements(prob, adjacent=True)
     Me, Le = _segment_matrices() if prob.dim == 2 else _quad_matrices()
+    if weighted:
+        Ev = prob.E if E is None else E
+        wts = 0.5 * (Ev[adj[:, 0]] + Ev[adj[:, 1]])
+    else:
+        wts = np.ones(len(els))
     m = els.shape[1]
     rows = np.repeat(els, m, axis=1).reshape(-1)
     cols = np.tile(els, (1, m)).reshape(-1)
     N = prob.n_nodes
-    M = sp.coo_matrix((np.tile(Me.reshape(-1), len(els)), (rows, cols)),
+    M = sp.coo_matrix(((wts[:, None] * Me.reshape(1, -1)).reshape(-1), (rows, cols)),
                       shape=(N, N)).tocsr()
-    L = sp.coo_matrix((np.tile(Le.reshape(-1), len(els)), (rows, cols)),
+    L = sp.coo_matrix(((wts[:, None] * Le.reshape(1, -1)).reshape(-1), (rows, cols)),
                       shape=(N, N)).tocsr()
     cls = dd.classify(prob)
     g = np.flatnonzero(cls == dd.GAMMA)

@@ -144,12 +144,13 @@ def full_operator(op):
 
 
 def schur_pcg(prob, precond="I", theta=0.5, tol=1e-10, maxit=2000,
-              lanczos_tol=1e-2, kmax=20, flexible=None, E=None):
+              lanczos_tol=1e-2, kmax=20, flexible=None, E=None, weighted=False):
     """Interface solve on the CPU.  Returns (u, iterations, history).
 
     precond: "I" (no interface preconditioner), "htilde" (dense closed form
     of Hhat_theta with consistent M), "htilde_lumped" (dense, lumped M),
-    "lanczos" (inverse Lanczos, lumped M, exact L solves).
+    "lanczos" (inverse Lanczos, lumped M, exact L solves).  ``weighted``
+    builds M and L with the modulus weighting of iface.skeleton_matrices.
     """
     op = dd.SchurOperator(prob, E)
     g = op.rhs()
@@ -159,13 +160,14 @@ def schur_pcg(prob, precond="I", theta=0.5, tol=1e-10, maxit=2000,
     if precond == "I":
         P = None
     elif precond in ("htilde", "htilde_lumped"):
-        M, L, _ = iface.skeleton_matrices(prob, lumped=precond.endswith("lumped"))
+        M, L, _ = iface.skeleton_matrices(prob, lumped=precond.endswith("lumped"),
+                                          weighted=weighted, E=E)
         Hi = iface.htilde_inv(M, L, theta)
 
         def P(r):
             return iface.componentwise(Hi, r, d)
     elif precond == "lanczos":
-        M, L, _ = iface.skeleton_matrices(prob, lumped=True)
+        M, L, _ = iface.skeleton_matrices(prob, lumped=True, weighted=weighted, E=E)
 
         def P(r):
             R = r.reshape(-1, d)

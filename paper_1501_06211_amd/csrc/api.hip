@@ -74,6 +74,45 @@ int sync_check(edd_problem *p) {
   return check_hip(p, e);
 }
 
+static hipEvent_t kt_event(edd_problem *p) {
+  if (!p->kt_pool.empty()) {
+    hipEvent_t e = p->kt_pool.back();
+    p->kt_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static void kt_resolve(edd_problem *p) {
+  for (auto &pd : p->kt_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pd.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
+      p->kt_count[pd.kind] += 1;
+      p->kt_ms[pd.kind] += ms;
+    }
+    p->kt_pool.push_back(pd.a);
+    p->kt_pool.push_back(pd.b);
+  }
+  p->kt_pending.clear();
+}
+
+KTimer::KTimer(edd_problem *p_, int kind_) : p(p_), kind(kind_) {
+  if (!p->kt_enabled) return;
+  a = kt_event(p);
+  b = kt_event(p);
+  if (a && b) hipEventRecord(a, p->stream);
+}
+
+KTimer::~KTimer() {
+  if (!p->kt_enabled || !a || !b) return;
+  hipEventRecord(b, p->stream);
+  p->kt_pending.push_back({kind, a, b});
+  if (p->kt_pending.size() > 4096) kt_resolve(p);
+}
+
 // y = S v on interface vectors
 void apply_S(edd_problem *p, const double *v, double *y, int prec) {
   double *t = p->w_I[2];
@@ -403,6 +442,8 @@ int edd_destroy(edd_problem *p) {
     else hipFree(ptr);
   }
   if (p->scal_h) hipHostFree(p->scal_h);
+  kt_resolve(p);
+  for (hipEvent_t e : p->kt_pool) hipEventDestroy(e);
   delete p;
   return EDD_OK;
 }
@@ -452,7 +493,7 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
   int lds = 0;
   hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
   p->lds_limit = lds > 0 ? (size_t)lds : 65536;
-  if (p->max_kd + 32 > 2048 ||
+  if (p->max_kd + 32 > 1024 ||
       band_solve_lds_bytes(p, EDD_F64) > p->lds_limit) {
     delete p;
     return EDD_EINVAL;  // subdomains too large for one workgroup
@@ -466,9 +507,23 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
   EDD_TRY_ALLOC(p->order_d, int, p->n_sub);
   EDD_TRY_ALLOC(p->info_d, int, p->n_sub);
   EDD_TRY_ALLOC(p->E_d, double, p->n_el);
-  EDD_TRY_ALLOC(p->fac64_d, double, std::max<int64_t>(1, p->fac_entries));
-  if (p->factor_precision & EDD_F32)
-    EDD_TRY_ALLOC(p->fac32_d, float, std::max<int64_t>(1, p->fac_entries));
+  {
+    // band storage with padding on both sides (unconditional panel loads)
+    const int64_t padded = kBandPadFront + p->fac_entries + band_pad_back(p->max_kd);
+    double *f64 = nullptr, *r64 = nullptr;
+    EDD_TRY_ALLOC(f64, double, padded);
+    EDD_TRY_ALLOC(r64, double, padded);
+    p->fac64_d = f64 + kBandPadFront;
+    p->rac64_d = r64 + kBandPadFront;
+    p->fac_padded = padded;
+    if (p->factor_precision & EDD_F32) {
+      float *f32 = nullptr, *r32 = nullptr;
+      EDD_TRY_ALLOC(f32, float, padded);
+      EDD_TRY_ALLOC(r32, float, padded);
+      p->fac32_d = f32 + kBandPadFront;
+      p->rac32_d = r32 + kBandPadFront;
+    }
+  }
   for (int i = 0; i < 3; ++i) EDD_TRY_ALLOC(p->w_I[i], double, std::max<int64_t>(1, p->n_idofs));
   for (int i = 0; i < 8; ++i) EDD_TRY_ALLOC(p->w_G[i], double, std::max<int64_t>(1, p->n_gamma * D));
   for (int i = 0; i < 2; ++i) EDD_TRY_ALLOC(p->w_full[i], double, p->ndof);
@@ -497,6 +552,13 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) { edd_destroy(p); return EDD_EHIP; }
   launch_fill(p, p->ndof, 0.0, p->w_full[1]);
+  // padding is read (and discarded) by the band kernels: keep it finite
+  launch_fill(p, p->fac_padded, 0.0, p->fac64_d - kBandPadFront);
+  launch_fill(p, p->fac_padded, 0.0, p->rac64_d - kBandPadFront);
+  if (p->fac32_d) {
+    launch_fill_f32(p, p->fac_padded, p->fac32_d - kBandPadFront);
+    launch_fill_f32(p, p->fac_padded, p->rac32_d - kBandPadFront);
+  }
   rc = precond_setup(p);
   if (rc) { edd_destroy(p); return rc; }
   rc = sync_check(p);
@@ -525,7 +587,7 @@ int edd_set_element_moduli(edd_problem *p, const void *E_dev, int dtype) {
   if (e != hipSuccess) return check_hip(p, e);
   for (int v : info)
     if (v) return EDD_ENOTSPD;
-  if (p->factor_precision & EDD_F32) launch_band_to_f32(p);
+  launch_band_layouts(p);
   rc = sync_check(p);
   if (rc) return rc;
   p->have_moduli = true;
@@ -581,12 +643,33 @@ int edd_get_info(edd_problem *p, edd_info *info) {
   info->n_el = p->n_el;
   info->n_gamma = p->n_gamma;
   info->n_interior_dofs = p->n_idofs;
-  info->factor_entries = p->fac_entries;
+  info->factor_entries = p->fac_entries_real;
   info->max_band = p->max_kd;
   info->max_sub_dofs = p->max_n;
   info->skeleton_faces = p->n_faces;
   info->face_classes = p->n_face_classes;
   info->theta_default = p->theta_default;
+  return EDD_OK;
+}
+
+int edd_set_kernel_timing(edd_problem *p, int enable) {
+  if (!p) return EDD_EINVAL;
+  kt_resolve(p);
+  p->kt_enabled = enable != 0;
+  for (int k = 0; k < EDD_KT_COUNT; ++k) {
+    p->kt_count[k] = 0;
+    p->kt_ms[k] = 0.0;
+  }
+  return EDD_OK;
+}
+
+int edd_get_kernel_times(edd_problem *p, edd_kernel_times *t) {
+  if (!p || !t) return EDD_EINVAL;
+  kt_resolve(p);
+  for (int k = 0; k < EDD_KT_COUNT; ++k) {
+    t->count[k] = p->kt_count[k];
+    t->total_ms[k] = p->kt_ms[k];
+  }
   return EDD_OK;
 }
 

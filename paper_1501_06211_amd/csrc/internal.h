@@ -35,10 +35,11 @@ struct Geom {
 struct SubDesc {
   int n;       // interior dofs
   int kd;      // half bandwidth
+  int np;      // n rounded up to a multiple of 64; rows n..np-1 of the band
+               // hold an identity block so every 64-row block is full
   int len[3];  // box length along local axes (fast, mid, slow)
   int ax[3];   // global axis of each local axis
   int lo[3];   // box origin, indexed by global axis
-  int pad;
   int64_t dof_off;  // offset in interior vectors
   int64_t fac_off;  // offset in band storage (entries)
 };
@@ -70,7 +71,8 @@ struct edd_problem {
   std::vector<int> order;  // launch order of subdomains (largest first)
   std::vector<int> inode, gnode, nmap_host;
   int64_t fac_entries = 0;
-  int max_kd = 0, max_n = 0;
+  int max_kd = 0, max_n = 0, max_np = 0;
+  int64_t fac_entries_real = 0;  // band entries without the padding rows
   double K0[24 * 24];
   double theta_default = 0.5;
 
@@ -95,8 +97,11 @@ struct edd_problem {
   int *order_d = nullptr;
   int *info_d = nullptr;     // per-subdomain factorisation status
   double *E_d = nullptr;     // element moduli (FP64 copy)
-  double *fac64_d = nullptr;
+  double *fac64_d = nullptr;  // band storage (padded allocation)
+  int64_t fac_padded = 0;
   float *fac32_d = nullptr;
+  double *rac64_d = nullptr;  // row-major copies used by the backward sweep
+  float *rac32_d = nullptr;
   bool have_moduli = false;
 
   // skeleton operators (CSR of L, lumped mass, face blocks)
@@ -134,6 +139,14 @@ struct edd_problem {
   size_t outer_len = 0;
 
   int last_hip_error = 0;
+
+  // kernel timing (edd_set_kernel_timing)
+  bool kt_enabled = false;
+  struct Pending { int kind; hipEvent_t a, b; };
+  std::vector<Pending> kt_pending;
+  std::vector<hipEvent_t> kt_pool;
+  int64_t kt_count[EDD_KT_COUNT] = {};
+  double kt_ms[EDD_KT_COUNT] = {};
 };
 
 namespace edd {
@@ -156,7 +169,7 @@ void launch_mask_dirichlet(edd_problem *p, double *v);
 
 // kernels_band.hip
 void launch_band_cholesky(edd_problem *p);
-void launch_band_to_f32(edd_problem *p);
+void launch_band_layouts(edd_problem *p);
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x);
 
@@ -170,6 +183,7 @@ void launch_axpby(edd_problem *p, int64_t n, double a, const double *x,
                   double b, double *y);
 void launch_copy(edd_problem *p, int64_t n, const double *x, double *y);
 void launch_fill(edd_problem *p, int64_t n, double v, double *y);
+void launch_fill_f32(edd_problem *p, int64_t n, float *y);
 // x += alpha*pv; r -= alpha*q with alpha = scal[num]/scal[den]
 // also writes r.r to scal[slot] and copies scal[den] to scal[copy_dst]
 void launch_cg_update(edd_problem *p, int64_t n, int num, int den,
@@ -177,6 +191,9 @@ void launch_cg_update(edd_problem *p, int64_t n, int num, int den,
                       const double *q, int slot, int copy_dst);
 void launch_reduce(edd_problem *p, int nblocks, int stride, int nout, int slot);
 size_t band_solve_lds_bytes(const edd_problem *p, int precision);
+// padding (entries) around band storage; see kernels_band.hip
+constexpr int64_t kBandPadFront = 128;
+int64_t band_pad_back(int max_kd);
 void element_matrix(int dim, double nu, double *K0);
 double default_theta(int nsub);
 int build_geometry(edd_problem *p, const edd_mesh_desc *d);
@@ -197,6 +214,15 @@ int precond_apply(edd_problem *p, const double *r, double *z,
                   const edd_solve_opts *o, edd_solve_stats *st,
                   bool low_precision);
 int precond_setup(edd_problem *p);
+
+// Records HIP events around the launches in its scope when timing is on.
+struct KTimer {
+  edd_problem *p;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  KTimer(edd_problem *p_, int kind_);
+  ~KTimer();
+};
 
 // helpers (api.hip)
 void *dev_alloc(edd_problem *p, size_t bytes);

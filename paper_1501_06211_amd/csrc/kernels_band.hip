@@ -7,290 +7,406 @@
 // (the order array), so that round-robin dispatch over the XCDs spreads the
 // large blocks evenly.
 //
-// Factorisation (right-looking, panel width NB): a panel of NB columns and
-// the NB + kd rows it touches is held in registers, one window row per
-// thread slot; the panel is factorised column by column with two barriers
-// per column, written back, and the trailing band triangle is updated in
-// chunks of CH columns whose panel rows are staged through LDS.
+// Factorisation: left-looking band Cholesky, see k_band_cholesky.
 //
-// Substitution (panel width NB): the whole right-hand side of the subdomain
-// lives in LDS.  Forward: one wavefront solves the NB x NB diagonal
-// triangle with lane shuffles, then all threads apply the panel to the next
-// kd rows (coalesced column reads of the band).  Backward: each wavefront
-// reduces the dot products of NB columns with the already-known part of x,
-// then one wavefront solves the transposed diagonal triangle.
+// Substitution: the whole right-hand side of a subdomain lives in LDS.  The
+// forward sweep reads the factor by columns, the backward sweep a row-major
+// copy of it, so both are "update" sweeps with coalesced loads and no
+// reductions; both copies store reciprocal diagonals.
+//
+// The band storage is padded before the first and after the last subdomain
+// (kBandPadFront / band_pad_back entries), so panel loads are issued
+// unconditionally and out-of-band values are discarded with a select; only
+// stores are predicated.  This keeps many loads in flight per thread.
 #include "internal.h"
 
 namespace edd {
 namespace {
 
+template <typename T>
+__device__ inline T lane_bcast(T v, int lane);
+template <>
+__device__ inline double lane_bcast<double>(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <>
+__device__ inline float lane_bcast<float>(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 // ---------------------------------------------------------------------------
-// Band Cholesky
+// Band Cholesky, left-looking.  One thread owns one row of the current
+// window (NB panel columns plus the kd rows below them).  For each panel:
+//   acc[w, c] = A[j0+w, j0+c] - sum_{k < j0} L[j0+w, k] L[j0+c, k]
+// with the L[j0+c, k] (c < NB) staged through LDS in chunks of KC columns
+// and the L[j0+w, k] streamed from the band, then the diagonal block is
+// factored by wavefront 0 (readlane broadcasts) and the rows below solved
+// against it.  Only the panel's own columns are written.
 // ---------------------------------------------------------------------------
-template <int NB, int NT, int RPT, int CH>
+template <int NB, int NT, int KC, int RPT>
 __global__ __launch_bounds__(NT) void k_band_cholesky(
     const SubDesc *__restrict__ subs, const int *__restrict__ order,
     double *__restrict__ fac, int *__restrict__ info) {
-  __shared__ double colbuf[NB];
-  __shared__ double chunk[CH][NB + 1];
+  static_assert(NB <= 64, "wavefront 0 factors the diagonal block");
+  __shared__ double U[KC][NB];
+  __shared__ double Dl[NB][NB + 1];
+  __shared__ double Dinv[NB];
+  __shared__ int anybad;
   const SubDesc s = subs[order[blockIdx.x]];
-  const int n = s.n, kd = s.kd, ld = kd + 1;
+  const int n = s.np, kd = s.kd, ld = kd + 1;  // n is a multiple of NB
   double *L = fac + s.fac_off;
   const int tid = threadIdx.x;
-  int bad = 0;
-  double P[RPT][NB];
+  if (tid == 0) anybad = 0;
 
   for (int j0 = 0; j0 < n; j0 += NB) {
-    const int jn = min(NB, n - j0);
-    const int W = min(jn + kd, n - j0);  // window rows (relative to j0)
-    // load the panel
+    const int W = min(NB + kd, n - j0);
+    // rows w = tid + k*NT of the window are owned by this thread
+    double acc[RPT][NB];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int w = tid + k * NT;
+      const double *rowp = L + (int64_t)j0 * ld + w;  // (j0+w, j0+c) at rowp + c*kd
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        const bool ok = (w < W) && (c < jn) && (w >= c) && (w - c <= kd);
-        P[k][c] = ok ? L[(int64_t)(j0 + c) * ld + (w - c)] : 0.0;
+        const double v = rowp[c * kd];
+        acc[k][c] = (w < W && c <= w && w - c <= kd) ? v : 0.0;
       }
     }
-    // factorise the panel column by column
+    // left-looking update from columns [kbeg, j0): each U value read from
+    // LDS serves the RPT rows of the thread
+    const int kbeg = max(0, j0 - kd);
+    const int kfirst = j0 + tid - kd;  // first nonzero column of row tid
+    for (int kc = kbeg; kc < j0; kc += KC) {
+      const int kn = min(KC, j0 - kc);
+      __syncthreads();
+      for (int e = tid; e < KC * NB; e += NT) {
+        const int kk = e / NB, c = e - kk * NB, k = kc + kk;
+        const double v = L[(int64_t)k * ld + (j0 + c - k)];
+        U[kk][c] = (kk < kn && j0 + c - k <= kd) ? v : 0.0;
+      }
+      __syncthreads();
+      if (tid < W && kc + kn > kfirst) {
+        for (int ks = 0; ks < kn; ks += 8) {
+          if (kc + ks + 8 <= kfirst) continue;
+          double lw[RPT][8];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c < jn) {
+          for (int k = 0; k < RPT; ++k) {
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-          const int w = tid + k * NT;
-          if (w >= c && w < jn) colbuf[w] = P[k][c];
-        }
-        __syncthreads();
-        const double piv = colbuf[c];
-        if (!(piv > 0.0)) bad = 1;
-        const double d = sqrt(piv > 0.0 ? piv : 1.0);
-        const double rd = 1.0 / d;
+            for (int u = 0; u < 8; ++u) {
+              const int kk = kc + ks + u;
+              lw[k][u] = L[(int64_t)kk * ld + (j0 + tid + k * NT - kk)];
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-          const int w = tid + k * NT;
-          if (w == c) {
-            P[k][c] = d;
-          } else if (w > c && w < W) {
-            const double l = P[k][c] * rd;
-            P[k][c] = l;
+          for (int k = 0; k < RPT; ++k) {
+            const int w = tid + k * NT;
 #pragma unroll
-            for (int c2 = c + 1; c2 < NB; ++c2)
-              if (c2 < jn) P[k][c2] = fma(-l, colbuf[c2] * rd, P[k][c2]);
+            for (int u = 0; u < 8; ++u) {
+              const int kk = kc + ks + u;
+              lw[k][u] = (ks + u < kn && kk >= j0 + w - kd && w < W) ? lw[k][u] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+              const double uc = U[ks + u][c];
+#pragma unroll
+              for (int k = 0; k < RPT; ++k) acc[k][c] = fma(-lw[k][u], uc, acc[k][c]);
+            }
           }
         }
-        __syncthreads();
       }
     }
-    // write the panel back
+    // Diagonal block: wavefront 0 eliminates the first NB columns of its 64
+    // rows with lane broadcasts and no per-lane predicates.  Rows w < NB end
+    // as the diagonal block of L, rows NB <= w < 64 as final panel rows
+    // (right-looking elimination of a row is its triangular solve); entries
+    // above the diagonal become garbage that is never read or written back.
+    if (tid < 64) {
+      const int w = tid;
+      bool bad = false;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double piv = lane_bcast(acc[0][c], c);
+        bad = bad || !(piv > 0.0);
+        const double dc = sqrt(piv > 0.0 ? piv : 1.0);
+        const double rd = 1.0 / dc;
+        acc[0][c] = (w == c) ? dc : acc[0][c] * rd;
+#pragma unroll
+        for (int j = c + 1; j < NB; ++j)
+          acc[0][j] = fma(-acc[0][c], lane_bcast(acc[0][c], j), acc[0][j]);
+        if (w == 0) Dinv[c] = rd;
+      }
+      if (bad && w == 0) anybad = 1;
+      if (w < NB) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) Dl[w][c] = acc[0][c];
+      }
+    }
+    __syncthreads();
+    // all other rows: solve against L_D^T, then write the panel back
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int w = tid + k * NT;
+      if (w < W && w >= 64) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        if (w < W && c < jn && w >= c && w - c <= kd)
-          L[(int64_t)(j0 + c) * ld + (w - c)] = P[k][c];
-      }
-    }
-    // trailing update: A[w, q] -= P[w,:] . P[q,:] for jn <= q <= w < W
-    for (int q0 = jn; q0 < W; q0 += CH) {
-      const int qe = min(q0 + CH, W);
+        for (int c = 0; c < NB; ++c) {
+          double x = acc[k][c];
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int w = tid + k * NT;
-        if (w >= q0 && w < qe) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) chunk[w - q0][c] = P[k][c];
+          for (int c2 = 0; c2 < c; ++c2) x = fma(-acc[k][c2], Dl[c][c2], x);
+          acc[k][c] = x * Dinv[c];
         }
       }
-      __syncthreads();
+      if (w < W) {
+        double *rowp = L + (int64_t)j0 * ld + w;
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int w = tid + k * NT;
-        if (w >= q0 && w < W) {
-          const int qmax = min(qe - 1, w);
-          for (int q = q0; q <= qmax; ++q) {
-            double acc = 0.0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) acc = fma(P[k][c], chunk[q - q0][c], acc);
-            double *a = L + (int64_t)(j0 + q) * ld + (w - q);
-            *a -= acc;
-          }
-        }
+        for (int c = 0; c < NB; ++c)
+          if (c <= w && w - c <= kd) rowp[c * kd] = acc[k][c];
       }
-      __syncthreads();
     }
   }
-  // report the first failing subdomain status (0 = ok)
-  __shared__ int anybad;
-  if (tid == 0) anybad = 0;
-  __syncthreads();
-  if (bad) anybad = 1;
   __syncthreads();
   if (tid == 0) info[order[blockIdx.x]] = anybad;
 }
 
-// ---------------------------------------------------------------------------
-// Substitutions
-// ---------------------------------------------------------------------------
-template <typename W>
-__device__ inline W wave_sum(W v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Solve layouts from the factor L (column band, true diagonal):
+//   Cs[p*ld + r] = L[p+r, p] with the diagonal replaced by 1/L[p,p]
+//   Rs[q*ld + k] = L[q, q-k]  with the diagonal replaced by 1/L[q,q]
+// Cs may alias L.  One block per (subdomain, tile of 64 rows q).
+template <typename T>
+__global__ __launch_bounds__(256) void k_solve_layouts(
+    const SubDesc *__restrict__ subs, const double *__restrict__ Lf,
+    T *__restrict__ Cs, T *__restrict__ Rs) {
+  const SubDesc s = subs[blockIdx.y];
+  const int n = s.np, kd = s.kd, ld = kd + 1;
+  const double *Lb = Lf + s.fac_off;
+  T *Cb = Cs + s.fac_off;
+  T *Rb = Rs + s.fac_off;
+  for (int q0 = blockIdx.x * 64; q0 < n; q0 += gridDim.x * 64) {
+    // rows q in [q0, q0+64): Rs[q*ld + k] = L[q - k][k] (column q-k, offset k)
+    for (int e = threadIdx.x; e < 64 * ld; e += blockDim.x) {
+      const int qq = e / ld, k = e - qq * ld, q = q0 + qq;
+      if (q >= n) continue;
+      const int p = q - k;
+      double v = 0.0;
+      if (p >= 0) v = Lb[(int64_t)p * ld + k];
+      if (k == 0) v = 1.0 / v;
+      Rb[(int64_t)q * ld + k] = (T)v;
+    }
+  }
+  __syncthreads();
+  const bool inplace = (const void *)Cs == (const void *)Lf;
+  for (int q0 = blockIdx.x * 64; q0 < n; q0 += gridDim.x * 64) {
+    if (inplace) {
+      // only the diagonal changes
+      for (int qq = threadIdx.x; qq < 64; qq += blockDim.x) {
+        const int p = q0 + qq;
+        if (p < n) Cb[(int64_t)p * ld] = (T)(1.0 / Lb[(int64_t)p * ld]);
+      }
+      continue;
+    }
+    for (int e = threadIdx.x; e < 64 * ld; e += blockDim.x) {
+      const int qq = e / ld, r = e - qq * ld, p = q0 + qq;
+      if (p >= n) continue;
+      double v = Lb[(int64_t)p * ld + r];
+      if (r == 0) v = 1.0 / v;
+      Cb[(int64_t)p * ld + r] = (T)v;
+    }
+  }
 }
 
-template <typename T, typename W, int NB, int NT>
+// ---------------------------------------------------------------------------
+// Substitutions.  Block b of 64 rows is owned by wavefront b mod NW (row i
+// by thread i mod NT), so the owner can solve its diagonal block with the
+// values it updated itself; one barrier per block publishes the block.
+// ---------------------------------------------------------------------------
+template <typename T, typename W, int NT>
 __global__ __launch_bounds__(NT) void k_band_solve(
     const SubDesc *__restrict__ subs, const int *__restrict__ order,
-    const T *__restrict__ fac, const double *__restrict__ b,
-    double *__restrict__ x, int maxn) {
+    const T *__restrict__ Cs, const T *__restrict__ Rs,
+    const double *__restrict__ b, double *__restrict__ x) {
+  constexpr int NB = 64;
+  constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   W *xs = reinterpret_cast<W *>(smem);
-  T *dblk = reinterpret_cast<T *>(smem + ((sizeof(W) * maxn + 15) / 16) * 16);
-  constexpr int PITCH = NB + 1;
-  constexpr int NW = NT / 64;
   const SubDesc s = subs[order[blockIdx.x]];
-  const int n = s.n, kd = s.kd, ld = kd + 1;
-  const T *L = fac + s.fac_off;
+  const int n = s.n, np = s.np, kd = s.kd, ld = kd + 1;
+  const T *C = Cs + s.fac_off;
+  const T *R = Rs + s.fac_off;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nblk = np / NB;
 
-  for (int i = tid; i < n; i += NT) xs[i] = (W)b[s.dof_off + i];
+  for (int i = tid; i < np; i += NT) xs[i] = i < n ? (W)b[s.dof_off + i] : (W)0;
   __syncthreads();
 
-  // ---- forward: L y = b ----
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int jn = min(NB, n - j0);
-    // diagonal block, column-major with pitch: dblk[c*PITCH + row]
-    for (int e = tid; e < NB * NB; e += NT) {
-      const int c = e / NB, row = e - c * NB, r = row - c;
-      const bool ok = r >= 0 && c < jn && row < jn && r <= kd;
-      dblk[c * PITCH + row] = ok ? L[(int64_t)(j0 + c) * ld + r] : (T)0;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      W xi = lane < jn ? xs[j0 + lane] : (W)0;
+  // ---- forward: L y = b (column layout) ----
+  for (int bk = 0; bk < nblk; ++bk) {
+    const int j0 = bk * NB;
+    if (wave == bk % NW) {
+      // diagonal block: lane i keeps s[c] = L[j0+i, j0+c] for c < i and its
+      // own reciprocal pivot dd; step c broadcasts y_c = x_c * d_c.  No
+      // per-lane predicates live across the chain.
+      const int i = lane;
+      const T *rowp = C + (int64_t)j0 * ld + i;  // (j0+i, j0+c) at rowp + c*kd
+      T sv[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) sv[c] = rowp[c * kd];
+      __builtin_amdgcn_sched_barrier(0);
+      W dd = 0;
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        if (c < jn) {
-          if (lane == c) xi = xi / (W)dblk[c * PITCH + c];
-          const W xc = __shfl(xi, c, 64);
-          if (lane > c && lane < NB) xi -= (W)dblk[c * PITCH + lane] * xc;
-        }
+        dd = (c == i) ? (W)sv[c] : dd;
+        sv[c] = (c < i && i - c <= kd) ? sv[c] : (T)0;
       }
-      if (lane < jn) xs[j0 + lane] = xi;
+      W xi = xs[j0 + i];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
+        xi = fma(-(W)sv[c], yc, xi);
+      }
+      xs[j0 + i] = xi * dd;
     }
     __syncthreads();
-    const int rend = min(n, j0 + jn + kd);
-    for (int i = j0 + jn + tid; i < rend; i += NT) {
+    const int r0 = j0 + NB, r1 = min(np, j0 + NB + kd);
+    // rows r0 <= i < r1 owned by this thread: i = tid (mod NT)
+    for (int i = r0 + ((tid - r0) % NT + NT) % NT; i < r1; i += NT) {
+      const T *rowp = C + (int64_t)j0 * ld + (i - j0);
+      const int cmin = i - j0 - kd;  // first block column inside the band
+      T v[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v[c] = rowp[c * kd];
+      __builtin_amdgcn_sched_barrier(0);
       W acc = 0;
-      const int c0 = max(0, i - j0 - kd);
-      for (int c = c0; c < jn; ++c)
-        acc += (W)L[(int64_t)(j0 + c) * ld + (i - j0 - c)] * xs[j0 + c];
+      if (cmin <= 0) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc = fma((W)v[c], xs[j0 + c], acc);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc = fma(c >= cmin ? (W)v[c] : (W)0, xs[j0 + c], acc);
+      }
       xs[i] -= acc;
     }
-    __syncthreads();
   }
+  __syncthreads();
 
-  // ---- backward: L^T x = y ----
-  const int jlast = ((n - 1) / NB) * NB;
-  for (int j0 = jlast; j0 >= 0; j0 -= NB) {
-    const int jn = min(NB, n - j0);
-    for (int cc = wave; cc < jn; cc += NW) {
-      const int c = j0 + cc;
-      const int rs = j0 + jn - c;
-      const int re = min(kd, n - 1 - c);
-      W acc = 0;
-      for (int r = rs + lane; r <= re; r += 64)
-        acc += (W)L[(int64_t)c * ld + r] * xs[c + r];
-      acc = wave_sum(acc);
-      if (lane == 0) xs[c] -= acc;
-    }
-    // diagonal block, row-major with pitch: dblk[row*PITCH + c]
-    for (int e = tid; e < NB * NB; e += NT) {
-      const int c = e / NB, row = e - c * NB, r = row - c;
-      const bool ok = r >= 0 && c < jn && row < jn && r <= kd;
-      dblk[row * PITCH + c] = ok ? L[(int64_t)(j0 + c) * ld + r] : (T)0;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      W xi = lane < jn ? xs[j0 + lane] : (W)0;
+  // ---- backward: L^T x = y (row layout) ----
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int j0 = bk * NB;
+    if (wave == bk % NW) {
+      const int i = lane;
+      // L[j0+c, j0+i] = R[(j0+c)*ld + (c-i)] at colp + c*(ld+1)
+      const T *colp = R + (int64_t)j0 * ld - i;
+      T sv[NB];
 #pragma unroll
-      for (int cc = NB - 1; cc >= 0; --cc) {
-        if (cc < jn) {
-          if (lane == cc) xi = xi / (W)dblk[cc * PITCH + cc];
-          const W xc = __shfl(xi, cc, 64);
-          if (lane < cc) xi -= (W)dblk[cc * PITCH + lane] * xc;
-        }
+      for (int c = 0; c < NB; ++c) sv[c] = colp[c * (ld + 1)];
+      __builtin_amdgcn_sched_barrier(0);
+      W dd = 0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        dd = (c == i) ? (W)sv[c] : dd;
+        sv[c] = (c > i && c - i <= kd) ? sv[c] : (T)0;
       }
-      if (lane < jn) xs[j0 + lane] = xi;
+      W xi = xs[j0 + i];
+#pragma unroll
+      for (int c = NB - 1; c >= 0; --c) {
+        const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
+        xi = fma(-(W)sv[c], yc, xi);
+      }
+      xs[j0 + i] = xi * dd;
     }
     __syncthreads();
+    const int r0 = max(0, j0 - kd), r1 = j0;
+    for (int i = r0 + ((tid - r0) % NT + NT) % NT; i < r1; i += NT) {
+      // L[j0+c, i] = R[(j0+c)*ld + (j0+c-i)] at rowp + c*(ld+1)
+      const T *rowp = R + (int64_t)j0 * ld + (j0 - i);
+      const int cmax = kd - (j0 - i);  // last block column inside the band
+      T v[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) v[c] = rowp[c * (ld + 1)];
+      __builtin_amdgcn_sched_barrier(0);
+      W acc = 0;
+      if (cmax >= NB - 1) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc = fma((W)v[c], xs[j0 + c], acc);
+      } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc = fma(c <= cmax ? (W)v[c] : (W)0, xs[j0 + c], acc);
+      }
+      xs[i] -= acc;
+    }
   }
+  __syncthreads();
   for (int i = tid; i < n; i += NT) x[s.dof_off + i] = (double)xs[i];
 }
 
-__global__ void k_f64_to_f32(const double *__restrict__ a, float *__restrict__ b,
-                             int64_t n) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-       t += (int64_t)gridDim.x * blockDim.x)
-    b[t] = (float)a[t];
-}
-
-template <int NB, int NT, int RPT>
+template <int NT, int RPT>
 void chol_launch(edd_problem *p) {
-  k_band_cholesky<NB, NT, RPT, 32><<<p->n_sub, NT, 0, p->stream>>>(
+  k_band_cholesky<32, NT, 64, RPT><<<p->n_sub, NT, 0, p->stream>>>(
       p->subs_d, p->order_d, p->fac64_d, p->info_d);
 }
 
-template <typename T, typename W, int NB, int NT>
-void solve_launch(edd_problem *p, const T *fac, const double *b, double *x) {
-  const size_t lds = ((sizeof(W) * p->max_n + 15) / 16) * 16 +
-                     sizeof(T) * NB * (NB + 1);
+template <typename T, typename W, int NT>
+void solve_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x) {
+  const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
   static bool attr_set = false;  // per instantiation
   if (!attr_set) {
-    hipFuncSetAttribute((const void *)k_band_solve<T, W, NB, NT>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds > 65536 ? 163840 : 65536);
+    hipFuncSetAttribute((const void *)k_band_solve<T, W, NT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
     attr_set = true;
   }
-  k_band_solve<T, W, NB, NT><<<p->n_sub, NT, lds, p->stream>>>(
-      p->subs_d, p->order_d, fac, b, x, p->max_n);
+  k_band_solve<T, W, NT><<<p->n_sub, NT, lds, p->stream>>>(p->subs_d, p->order_d,
+                                                          C, R, b, x);
 }
 
 }  // namespace
 
+int64_t band_pad_back(int max_kd) {
+  // largest overrun of an unconditional load past the last column
+  return (int64_t)(64 + 2) * (max_kd + 2) + 64 * 64 + 1024;
+}
+
 size_t band_solve_lds_bytes(const edd_problem *p, int precision) {
-  const int NB = p->max_kd > 96 ? 64 : 32;
   const size_t ws = precision == EDD_F32 ? 4 : 8;
-  return ((ws * p->max_n + 15) / 16) * 16 + ws * NB * (NB + 1);
+  return ((ws * p->max_np + 15) / 16) * 16;
 }
 
 void launch_band_cholesky(edd_problem *p) {
-  constexpr int NB = 32;
-  const int W = NB + p->max_kd;
-  if (W <= 128) chol_launch<NB, 128, 1>(p);
-  else if (W <= 256) chol_launch<NB, 256, 1>(p);
-  else if (W <= 512) chol_launch<NB, 512, 1>(p);
-  else if (W <= 1024) chol_launch<NB, 512, 2>(p);
-  else if (W <= 1536) chol_launch<NB, 512, 3>(p);
-  else chol_launch<NB, 512, 4>(p);  // kd up to 2016 (checked at setup)
+  KTimer kt(p, EDD_KT_BAND_CHOLESKY);
+  const int rows = 32 + p->max_kd;  // window rows
+  if (rows <= 64) chol_launch<64, 1>(p);
+  else if (rows <= 128) chol_launch<128, 1>(p);
+  else if (rows <= 256) chol_launch<128, 2>(p);
+  else if (rows <= 512) chol_launch<256, 2>(p);
+  else chol_launch<1024, 1>(p);  // kd <= 992 (checked at setup)
 }
 
-void launch_band_to_f32(edd_problem *p) {
-  k_f64_to_f32<<<2048, 256, 0, p->stream>>>(p->fac64_d, p->fac32_d,
-                                            p->fac_entries);
+// After the factorisation: build the solve layouts (FP64 always, FP32 when
+// requested).  The FP64 column layout overwrites the factor in place.
+void launch_band_layouts(edd_problem *p) {
+  KTimer kt(p, EDD_KT_LAYOUTS);
+  dim3 grid(64, p->n_sub);
+  if (p->fac32_d)
+    k_solve_layouts<float><<<grid, 256, 0, p->stream>>>(p->subs_d, p->fac64_d,
+                                                        p->fac32_d, p->rac32_d);
+  k_solve_layouts<double><<<grid, 256, 0, p->stream>>>(p->subs_d, p->fac64_d,
+                                                       p->fac64_d, p->rac64_d);
 }
 
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x) {
-  const bool big = p->max_kd > 96;
+  KTimer kt(p, EDD_KT_BAND_SOLVE);
+  const bool big = p->max_kd > 64;
   if (precision == EDD_F32) {
-    if (big) solve_launch<float, float, 64, 512>(p, p->fac32_d, b, x);
-    else solve_launch<float, float, 32, 64>(p, p->fac32_d, b, x);
+    if (big) solve_launch<float, float, 512>(p, p->fac32_d, p->rac32_d, b, x);
+    else solve_launch<float, float, 64>(p, p->fac32_d, p->rac32_d, b, x);
   } else {
-    if (big) solve_launch<double, double, 64, 512>(p, p->fac64_d, b, x);
-    else solve_launch<double, double, 32, 64>(p, p->fac64_d, b, x);
+    if (big) solve_launch<double, double, 512>(p, p->fac64_d, p->rac64_d, b, x);
+    else solve_launch<double, double, 64>(p, p->fac64_d, p->rac64_d, b, x);
   }
 }
 

@@ -131,7 +131,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(
 }
 
 // One thread per stored band entry (column p, offset r) of every subdomain:
-// K[q, p] with q = p + r, summed over the elements shared by the two nodes.
+// K[q, p] with q = p + r, summed over the elements shared by the two nodes;
+// padding columns p >= n get an identity diagonal.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_assemble_band(
     Geom g, const double *__restrict__ K0, const double *__restrict__ E,
@@ -140,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_band(
   constexpr int ND = D * NC;
   const SubDesc s = subs[blockIdx.y];
   const int ld = s.kd + 1;
-  const int64_t total = (int64_t)s.n * ld;
+  const int64_t total = (int64_t)s.np * ld;
   double *band = fac + s.fac_off;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -148,7 +149,9 @@ __global__ __launch_bounds__(kBlock) void k_assemble_band(
     const int r = (int)(e - (int64_t)p * ld);
     const int q = p + r;
     double val = 0.0;
-    if (q < s.n) {
+    if (p >= s.n) {
+      val = r == 0 ? 1.0 : 0.0;  // identity padding rows
+    } else if (q < s.n) {
       const int l1 = p / D, c1 = p - l1 * D;
       const int l2 = q / D, c2 = q - l2 * D;
       int loc1[3], loc2[3];
@@ -262,6 +265,7 @@ inline unsigned grid_for(int64_t n) {
 }  // namespace
 
 void launch_apply_full(edd_problem *p, const double *u, double *y) {
+  KTimer kt(p, EDD_KT_APPLY_K);
   Src s{u, nullptr, nullptr, 0.0, 0.0};
   const int64_t n = p->n_nodes;
   if (p->g.dim == 2)
@@ -277,6 +281,7 @@ void launch_apply_mapped(edd_problem *p, const int *tgt, int64_t ntgt,
                          double sG, const double *base_global, double sy,
                          double *out) {
   if (ntgt == 0) return;
+  KTimer kt(p, EDD_KT_APPLY_MAPPED);
   Src s{nullptr, xI, xG, sI, sG};
   if (p->g.dim == 2)
     k_apply<2, 1><<<grid_for(ntgt), kBlock, 0, p->stream>>>(
@@ -287,6 +292,7 @@ void launch_apply_mapped(edd_problem *p, const int *tgt, int64_t ntgt,
 }
 
 void launch_assemble_band(edd_problem *p) {
+  KTimer kt(p, EDD_KT_ASSEMBLE);
   dim3 grid(256, p->n_sub);
   if (p->g.dim == 2)
     k_assemble_band<2><<<grid, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d,

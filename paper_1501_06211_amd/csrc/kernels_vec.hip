@@ -69,6 +69,13 @@ __global__ __launch_bounds__(kBlock) void k_axpby(int64_t n, double a,
     y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_f32(int64_t n,
+                                                     float *__restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = 0.0f;
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double v,
                                                  double *__restrict__ y) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -190,6 +197,10 @@ void launch_copy(edd_problem *p, int64_t n, const double *x, double *y) {
 
 void launch_fill(edd_problem *p, int64_t n, double v, double *y) {
   k_fill<<<grid_for(n), kBlock, 0, p->stream>>>(n, v, y);
+}
+
+void launch_fill_f32(edd_problem *p, int64_t n, float *y) {
+  k_fill_f32<<<grid_for(n), kBlock, 0, p->stream>>>(n, y);
 }
 
 void launch_cg_update(edd_problem *p, int64_t n, int num, int den, double *x,

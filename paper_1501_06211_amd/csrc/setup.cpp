@@ -12,7 +12,8 @@
 // The interior nodes of a subdomain then form a box.  Each box is numbered
 // with its longest axis slowest and its shortest axis fastest, which keeps
 // the half bandwidth of K_{I_i I_i} at dim*(n_fast*n_mid + n_fast + 1) +
-// dim - 1.
+// dim - 1.  Each block is padded to a multiple of 64 rows with an identity
+// block so that the batched kernels only ever see full 64-row blocks.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -166,12 +167,15 @@ int build_geometry(edd_problem *p, const edd_mesh_desc *d) {
         else kd = D * (s.len[0] * s.len[1] + s.len[0] + 1) + D - 1;
         kd = std::max(0, std::min(kd, s.n - 1));
         s.kd = kd;
+        s.np = std::max(64, (s.n + 63) / 64 * 64);
         s.dof_off = dof_off;
         s.fac_off = fac_off;
         dof_off += s.n;
-        fac_off += (int64_t)s.n * (kd + 1);
+        fac_off += (int64_t)s.np * (kd + 1);
+        p->fac_entries_real += (int64_t)s.n * (kd + 1);
         p->max_kd = std::max(p->max_kd, kd);
         p->max_n = std::max(p->max_n, s.n);
+        p->max_np = std::max(p->max_np, s.np);
       }
   p->n_idofs = dof_off;
   p->n_inodes = dof_off / D;

@@ -29,8 +29,10 @@ EXPORTS = [
     "edd_apply_K", "edd_solve_interface", "edd_solve_interior", "edd_apply_S",
     "edd_apply_precond", "edd_get_info", "edd_get_gamma_nodes",
     "edd_get_interior_nodes", "edd_destroy", "edd_strerror",
-    "edd_last_hip_error",
+    "edd_last_hip_error", "edd_set_kernel_timing", "edd_get_kernel_times",
 ]
+KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
+            "precond", "layouts"]
 
 
 class EddError(RuntimeError):
@@ -104,6 +106,10 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64 * 8), ("total_ms", ctypes.c_double * 8)]
+
+
 ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
 FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -144,6 +150,8 @@ def lib():
     L.edd_strerror.argtypes = [i32]
     L.edd_strerror.restype = ctypes.c_char_p
     L.edd_last_hip_error.argtypes = [vp]
+    L.edd_set_kernel_timing.argtypes = [vp, i32]
+    L.edd_get_kernel_times.argtypes = [vp, ctypes.POINTER(KernelTimes)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("edd_default_opts", "edd_strerror"):
@@ -303,6 +311,17 @@ class Problem:
         out = np.zeros(self.n_interior_dofs // self.dim, dtype=np.int32)
         lib().edd_get_interior_nodes(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         return out
+
+    def set_kernel_timing(self, enable=True):
+        self._check(lib().edd_set_kernel_timing(self.h, int(enable)),
+                    "edd_set_kernel_timing")
+
+    def kernel_times(self):
+        t = KernelTimes()
+        self._check(lib().edd_get_kernel_times(self.h, ctypes.byref(t)),
+                    "edd_get_kernel_times")
+        return {n: (int(t.count[i]), float(t.total_ms[i]))
+                for i, n in enumerate(KT_NAMES)}
 
     def close(self):
         if getattr(self, "h", None):

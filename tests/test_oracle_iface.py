@@ -118,3 +118,31 @@ def test_face_block_pcg_solves_L(dim):
     assert np.linalg.norm(x - xr) <= 1e-9 * np.linalg.norm(xr)
     _, its_plain, _ = krylov.pcg(lambda v: L @ v, b, None, tol=1e-12, maxit=2000)
     assert its < its_plain
+
+
+def test_weighted_skeleton_constant_modulus_and_adjacency():
+    # with a constant modulus c the weighted operators are c times the
+    # unweighted ones; the two neighbours of every skeleton element straddle it
+    for p in (w.cantilever2d(24, 16, block=8),
+              w.cantilever3d(8, 8, 6, cuts=(w.even_cuts(8, 4), w.even_cuts(8, 4),
+                                            np.array([0, 3, 6])))):
+        p.E = np.full(p.n_el, 2.5)
+        M, L, _ = iface.skeleton_matrices(p, lumped=True)
+        Mw, Lw, _ = iface.skeleton_matrices(p, lumped=True, weighted=True)
+        assert abs(Mw - 2.5 * M).max() < 1e-14 and abs(Lw - 2.5 * L).max() < 1e-13
+        els, adj = iface.skeleton_elements(p, adjacent=True)
+        from oracle import fe
+        en = fe.element_nodes(p)
+        for q, (a, b) in zip(els[::7], adj[::7]):
+            assert set(q) <= set(en[a]) and set(q) <= set(en[b]) and a != b
+
+
+def test_weighted_htheta_helps_heterogeneous_interface():
+    # contrast 1e3 (SIMP map of a smooth field): the modulus-weighted
+    # interface norm is a much better preconditioner than the unweighted one
+    p = w.cantilever3d_simp(16, 8, 8, (w.even_cuts(16, 4), w.even_cuts(8, 4),
+                                      w.even_cuts(8, 4)), seed=3, ell=4.0)
+    _, its_u, _ = krylov.schur_pcg(p, precond="htilde_lumped", theta=0.5, tol=1e-8)
+    _, its_w, _ = krylov.schur_pcg(p, precond="htilde_lumped", theta=0.5, tol=1e-8,
+                                   weighted=True)
+    assert its_w < 0.6 * its_u

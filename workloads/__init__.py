@@ -15,6 +15,7 @@ from .gen import (  # noqa: F401
     cantilever3d,
     cantilever2d_uniform_64x32,
     cantilever2d_simp_512x256,
+    cantilever3d_simp,
     cantilever3d_simp_128x64x64,
     to_sequence_2d,
     batch_uneven_problem,
