@@ -101,9 +101,9 @@ typedef struct edd_solve_opts {
   int maxit;          /* max interface iterations (per inner solve if mixed)  */
   int precision;      /* EDD_MODE_F64 or EDD_MODE_MIXED                       */
   int precond;        /* EDD_PC_IDENTITY or EDD_PC_HTHETA                     */
-  double theta;       /* H_theta index in [0,1]; < 0 picks the default for   */
-                      /* the number of subdomains (0.5 at 4, 0.6 at 16,      */
-                      /* 0.7 at 64, 0.75 from 256, log-linear between)       */
+  double theta;       /* H_theta index in [0,1]; < 0 picks the value reported  */
+                      /* best for the number of subdomains (0.5 at 4, 0.6 at */
+                      /* 16, 0.7 at 64, 0.75 from 256, log-linear between)   */
   int lanczos_kmax;   /* max inverse-Lanczos steps per application           */
   double lanczos_tol; /* relative change that stops Lanczos early            */
   double inner_tol;   /* relative tolerance of the skeleton-Laplacian PCG    */
@@ -113,6 +113,9 @@ typedef struct edd_solve_opts {
   double mixed_inner_tol; /* mixed mode: interface tolerance of inner solves  */
   int flexible_window; /* directions kept by the flexible Krylov (0 = all,   */
                        /* capped at 256; 1 = short recurrence)               */
+  int interface_weighting; /* 0: M, L of the skeleton as in the paper;        */
+                           /* 1: each skeleton element scaled by the mean     */
+                           /*    modulus of its two neighbouring elements     */
 } edd_solve_opts;
 
 typedef struct edd_solve_stats {
@@ -142,10 +145,10 @@ typedef struct edd_info {
   double theta_default;
 } edd_info;
 
-/* Fill *o with the defaults: tol 1e-8, maxit 2000, FP64, Hhat_theta with the
- * default theta, kmax 20, lanczos_tol 1e-2, inner_tol 1e-3 (Section 4),
+/* Fill *o with the defaults: tol 1e-8, maxit 2000, FP64, Hhat_theta with
+ * theta 0.5, kmax 20, lanczos_tol 1e-2, inner_tol 1e-3 (Section 4),
  * inner_maxit 50, no initial guess, outer_maxit 20, mixed_inner_tol 1e-3,
- * flexible_window 0. */
+ * flexible_window 0, interface_weighting 1. */
 void edd_default_opts(edd_solve_opts *o);
 
 /* Build a problem handle from the grid, the subdomain cuts, nu and the
@@ -197,6 +200,18 @@ int edd_apply_S(edd_problem *p, const double *v_dev, double *y_dev,
  * (Section 3).  Synchronises when the preconditioner is Hhat_theta. */
 int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
                       const edd_solve_opts *o);
+
+/* Pieces of the interface preconditioner on Gamma vectors (all d
+ * components), for checking and composition (Section 3 and Section 4):
+ *   which 0: y = L x     (skeleton Laplacian, weighting as requested)
+ *   which 1: y = M x     (lumped skeleton mass)
+ *   which 2: y = B^{-1} x (L restricted to the faces, cross points removed)
+ *   which 3: y ~ L^{-1} x by PCG with B (relative tolerance tol, maxit)
+ * weighting as edd_solve_opts.interface_weighting (1 needs moduli).
+ * Synchronises for which 3. */
+int edd_apply_skeleton_op(edd_problem *p, int which, int weighting,
+                          const double *x_dev, double *y_dev, double tol,
+                          int maxit);
 
 /* Sizes of the problem. */
 int edd_get_info(edd_problem *p, edd_info *info);

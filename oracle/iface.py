@@ -21,7 +21,8 @@ Readings (the defining report is not available):
   elements on interface edges for 2D problems, bilinear quadrilaterals on
   interface faces for 3D problems, assembled across cross points, with the
   rows and columns of clamped nodes removed.  ``lumped=True`` replaces M by
-  its row-sum diagonal.
+  the diagonal of row sums of the assembled mass taken before the clamped
+  columns are removed (each node's share of the skeleton's length or area).
 * Inverse Lanczos: Lanczos on C = L^{-1} M in the M inner product, started
   from b = M^{-1} r; then H~^{-1} r = C^{1-theta} b ~ |b|_M Q_k T_k^{1-theta} e1
   with T_k^{1-theta} from the eigendecomposition of the small tridiagonal.
@@ -155,10 +156,14 @@ def skeleton_matrices(prob, lumped=False, weighted=False, E=None):
                       shape=(N, N)).tocsr()
     cls = dd.classify(prob)
     g = np.flatnonzero(cls == dd.GAMMA)
+    if lumped:
+        # row sums of the assembled mass, clamped columns included: each free
+        # node keeps its full share of the skeleton's length/area
+        Ml = sp.diags(np.asarray(M.sum(axis=1)).ravel()[g]).tocsr()
     M = M[g][:, g]
     L = L[g][:, g]
     if lumped:
-        M = sp.diags(np.asarray(M.sum(axis=1)).ravel()).tocsr()
+        M = Ml
     return M.tocsr(), L.tocsr(), g
 
 

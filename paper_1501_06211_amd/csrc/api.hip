@@ -407,7 +407,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->maxit = 2000;
   o->precision = EDD_MODE_F64;
   o->precond = EDD_PC_HTHETA;
-  o->theta = -1.0;
+  o->theta = 0.5;
   o->lanczos_kmax = 20;
   o->lanczos_tol = 1e-2;
   o->inner_tol = 1e-3;
@@ -416,6 +416,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->outer_maxit = 20;
   o->mixed_inner_tol = 1e-3;
   o->flexible_window = 0;
+  o->interface_weighting = 1;
 }
 
 const char *edd_strerror(int code) {
@@ -591,6 +592,7 @@ int edd_set_element_moduli(edd_problem *p, const void *E_dev, int dtype) {
   rc = sync_check(p);
   if (rc) return rc;
   p->have_moduli = true;
+  p->sk_state = -1;  // weighted interface operators must be rebuilt
   return EDD_OK;
 }
 
@@ -627,8 +629,20 @@ int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
     launch_copy(p, p->n_gamma * p->g.dim, r_dev, z_dev);
     return check_hip(p, hipGetLastError());
   }
+  if (o->interface_weighting && !p->have_moduli) return EDD_ESTATE;
+  if (o->lanczos_kmax < 1 || o->lanczos_kmax > 64 || o->inner_maxit < 1) return EDD_EINVAL;
   edd_solve_stats st{};
   int rc = precond_apply(p, r_dev, z_dev, o, &st, o->precision == EDD_MODE_MIXED);
+  if (rc) return rc;
+  return sync_check(p);
+}
+
+int edd_apply_skeleton_op(edd_problem *p, int which, int weighting,
+                          const double *x_dev, double *y_dev, double tol, int maxit) {
+  if (!p || !x_dev || !y_dev || which < 0 || which > 3) return EDD_EINVAL;
+  if (weighting && !p->have_moduli) return EDD_ESTATE;
+  if (which == 3 && (maxit < 1 || !(tol >= 0.0))) return EDD_EINVAL;
+  int rc = skeleton_op(p, which, weighting, x_dev, y_dev, tol, maxit);
   if (rc) return rc;
   return sync_check(p);
 }
@@ -694,6 +708,9 @@ int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
   else edd_default_opts(&o);
   if (!(o.tol > 0.0) || o.maxit < 1 || o.outer_maxit < 0) return EDD_EINVAL;
   if (o.precond != EDD_PC_IDENTITY && o.precond != EDD_PC_HTHETA) return EDD_EINVAL;
+  if (o.precond == EDD_PC_HTHETA &&
+      (o.lanczos_kmax < 1 || o.lanczos_kmax > 64 || o.inner_maxit < 1 || o.theta > 1.0))
+    return EDD_EINVAL;
   if (o.precision != EDD_MODE_F64 && o.precision != EDD_MODE_MIXED) return EDD_EINVAL;
   if (o.precision == EDD_MODE_MIXED && !(p->factor_precision & EDD_F32)) return EDD_ESTATE;
   if (!(p->factor_precision & EDD_F64)) return EDD_ESTATE;

@@ -44,12 +44,6 @@ struct SubDesc {
   int64_t fac_off;  // offset in band storage (entries)
 };
 
-// Skeleton (interface) data for the H_theta preconditioner.
-struct FaceClass {
-  int m;           // nodes per face of this class
-  int64_t inv_off; // offset of the dense m x m inverse (row-major)
-};
-
 }  // namespace edd
 
 // The handle.  Everything below lives in host memory except the *_d
@@ -78,9 +72,6 @@ struct edd_problem {
 
   // skeleton / preconditioner (host side)
   int64_t sk_nnz = 0;
-  int n_faces = 0, n_face_classes = 0;
-  int64_t face_nodes_total = 0, face_inv_entries = 0;
-  int n_rest = 0;
 
   // device memory
   void *alloc_ctx = nullptr;
@@ -104,19 +95,35 @@ struct edd_problem {
   float *rac32_d = nullptr;
   bool have_moduli = false;
 
-  // skeleton operators (CSR of L, lumped mass, face blocks)
+  // skeleton operators of the interface preconditioner
+  int sk_state = -1;            // weighting the device operators hold (-1 none)
+  int64_t sk_n = 0;             // skeleton elements (edges 2D / faces 3D)
+  int sk_npe = 0;               // nodes per skeleton element
+  int *sk_adj_d = nullptr;      // [sk_n][2] neighbouring volume elements
+  double *sk_w_d = nullptr;     // [sk_n] element weights
   int *skL_rowptr_d = nullptr, *skL_col_d = nullptr;
-  double *skL_val_d = nullptr, *skM_d = nullptr, *skLdiag_d = nullptr;
-  int *face_ptr_d = nullptr;     // start of each face in face_node_d
-  int *face_class_d = nullptr;   // class of each face
-  int *face_node_d = nullptr;    // gamma indices of face nodes (class order)
-  int *rest_d = nullptr;         // gamma indices of cross-point nodes
-  double *face_inv_d = nullptr;  // dense inverses, all classes
-  float *face_inv32_d = nullptr;
-  std::vector<edd::FaceClass> classes;
-  std::vector<int> face_class_h, face_ptr_h;
-  edd::FaceClass *classes_d = nullptr;
-  int max_face_m = 0;
+  double *skL_val_d = nullptr;
+  int *skC_ptr_d = nullptr;     // contributions of each L entry
+  int *skC_elem_d = nullptr, *skC_ab_d = nullptr;
+  int *skN_ptr_d = nullptr, *skN_elem_d = nullptr;  // skeleton elements per node
+  double *skM_d = nullptr;      // lumped mass (diagonal)
+  double *skLdiag_d = nullptr;  // diagonal of L (current weighting)
+  double *skL0diag_d = nullptr; // diagonal of the unweighted L
+  double *skS_d = nullptr;      // face-block scaling sqrt(Ldiag / L0diag)
+  double sk_Le[16] = {}, sk_rowsum = 0.0;
+  int n_faces = 0, n_face_classes = 0, n_rest = 0, max_face_m = 0;
+  int *face_ptr_d = nullptr;    // [n_faces+1] start of each face in face_node
+  int *face_node_d = nullptr;   // gamma indices, node-id order inside a face
+  int *face_class_d = nullptr;  // class of each face
+  int64_t *class_off_d = nullptr;  // offset of each class inverse
+  int *rest_d = nullptr;        // gamma indices of cross-point nodes
+  double *face_inv_d = nullptr; // dense inverses of the unweighted face blocks
+  int64_t face_inv_entries = 0;
+  // Lanczos / inner PCG work space
+  int pc_kcap = 0;
+  double *pc_Q_d = nullptr;     // basis vectors
+  double *pc_v_d[8] = {};       // work vectors (gamma-sized)
+  double *pc_h = nullptr;       // pinned host buffer for coefficients
 
   // work buffers
   double *w_I[3] = {nullptr, nullptr, nullptr};  // interior vectors
@@ -214,6 +221,8 @@ int precond_apply(edd_problem *p, const double *r, double *z,
                   const edd_solve_opts *o, edd_solve_stats *st,
                   bool low_precision);
 int precond_setup(edd_problem *p);
+int skeleton_op(edd_problem *p, int which, int weighting, const double *x, double *y,
+                double tol, int maxit);
 
 // Records HIP events around the launches in its scope when timing is on.
 struct KTimer {

@@ -30,6 +30,7 @@ EXPORTS = [
     "edd_apply_precond", "edd_get_info", "edd_get_gamma_nodes",
     "edd_get_interior_nodes", "edd_destroy", "edd_strerror",
     "edd_last_hip_error", "edd_set_kernel_timing", "edd_get_kernel_times",
+    "edd_apply_skeleton_op",
 ]
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
             "precond", "layouts"]
@@ -69,6 +70,7 @@ class SolveOpts(ctypes.Structure):
         ("outer_maxit", ctypes.c_int),
         ("mixed_inner_tol", ctypes.c_double),
         ("flexible_window", ctypes.c_int),
+        ("interface_weighting", ctypes.c_int),
     ]
 
 
@@ -151,6 +153,7 @@ def lib():
     L.edd_strerror.restype = ctypes.c_char_p
     L.edd_last_hip_error.argtypes = [vp]
     L.edd_set_kernel_timing.argtypes = [vp, i32]
+    L.edd_apply_skeleton_op.argtypes = [vp, i32, i32, vp, vp, dbl, i32]
     L.edd_get_kernel_times.argtypes = [vp, ctypes.POINTER(KernelTimes)]
     for name in EXPORTS:
         f = getattr(L, name)
@@ -298,6 +301,15 @@ class Problem:
         o = default_opts(**opts)
         self._check(lib().edd_apply_precond(self.h, _ptr(r), _ptr(out), ctypes.byref(o)),
                     "edd_apply_precond")
+        return out
+
+    def skeleton_op(self, which, x, weighting=1, tol=1e-12, maxit=1000, out=None):
+        """which: 0 L, 1 M (lumped), 2 face-block preconditioner, 3 PCG solve."""
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(lib().edd_apply_skeleton_op(self.h, int(which), int(weighting), _ptr(x),
+                                                _ptr(out), float(tol), int(maxit)),
+                    "edd_apply_skeleton_op")
         return out
 
     def gamma_nodes(self):

@@ -1,0 +1,125 @@
+"""GPU interface preconditioner (inverse Lanczos for Hhat_theta) against the
+oracle's closed form and inverse-Lanczos reference, and end-to-end solves
+with it."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import fe, iface
+
+from gpu_util import make_problem, require_gpu, to_cuda, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _small2d():
+    rng = np.random.default_rng(21)
+    p = w.cantilever2d(24, 16, block=8)
+    p.E = 1e-3 + rng.uniform(0, 1, p.n_el) ** 3
+    return p
+
+
+def _small3d():
+    return w.cantilever3d_simp(8, 8, 6, (w.even_cuts(8, 4), w.even_cuts(8, 4),
+                                         np.array([0, 3, 6])), seed=5, ell=3.0)
+
+
+@pytest.mark.parametrize("weighted", [0, 1])
+@pytest.mark.parametrize("theta", [0.5, 0.7])
+def test_precond_matches_closed_form_2d(weighted, theta):
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _small2d()
+    prob = make_problem(p)
+    M, L, g = iface.skeleton_matrices(p, lumped=True, weighted=bool(weighted))
+    assert len(g) <= 64  # Lanczos reaches the whole space: closed form exactly
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal(len(g) * 2)
+    zref = iface.componentwise(iface.htilde_inv(M, L, theta), r, 2)
+    z = to_np(prob.apply_precond(to_cuda(r), precond=edd.PC_HTHETA, theta=theta,
+                                 lanczos_kmax=64, lanczos_tol=0.0, inner_tol=1e-14,
+                                 inner_maxit=1000, interface_weighting=weighted))
+    err = np.linalg.norm(z - zref) / np.linalg.norm(zref)
+    print(f"2D weighted={weighted} theta={theta}: rel err {err:.2e}")
+    assert err <= 1e-8
+    prob.close()
+
+
+@pytest.mark.parametrize("weighted", [0, 1])
+def test_precond_matches_oracle_lanczos_3d(weighted):
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _small3d()
+    prob = make_problem(p)
+    M, L, g = iface.skeleton_matrices(p, lumped=True, weighted=bool(weighted))
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(len(g) * 3)
+    R = r.reshape(-1, 3)
+    k = 12
+    zref = np.column_stack([iface.inverse_lanczos(M, L, 0.5, R[:, c], kmax=k, tol=0.0)[0]
+                            for c in range(3)]).reshape(-1)
+    z = to_np(prob.apply_precond(to_cuda(r), precond=edd.PC_HTHETA, theta=0.5,
+                                 lanczos_kmax=k, lanczos_tol=0.0, inner_tol=1e-14,
+                                 inner_maxit=2000, interface_weighting=weighted))
+    err = np.linalg.norm(z - zref) / np.linalg.norm(zref)
+    zc = iface.componentwise(iface.htilde_inv(M, L, 0.5), r, 3)
+    err_c = np.linalg.norm(z - zc) / np.linalg.norm(zc)
+    print(f"3D weighted={weighted}: vs oracle Lanczos {err:.2e}, vs closed form {err_c:.2e}")
+    assert err <= 1e-8
+    assert err_c <= 5e-2
+    prob.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_solve_htheta_parity(dim):
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _small2d() if dim == 2 else _small3d()
+    prob = make_problem(p)
+    uref = fe.solve_direct(p)
+    cref = fe.compliance(p.f, uref)
+    for weighted in (0, 1):
+        u, st = prob.solve(to_cuda(p.f), tol=1e-12, maxit=2000, precond=edd.PC_HTHETA,
+                           interface_weighting=weighted)
+        un = to_np(u)
+        err = np.linalg.norm(un - uref) / np.linalg.norm(uref)
+        cerr = abs(st["compliance"] - cref) / abs(cref)
+        print(f"{dim}D weighted={weighted}: its={st['iterations']} lanczos={st['lanczos_steps']} "
+              f"inner={st['inner_iterations']} u_err={err:.2e} c_err={cerr:.2e}")
+        assert err <= 1e-8 and cerr <= 1e-10
+    u_id, st_id = prob.solve(to_cuda(p.f), tol=1e-12, maxit=2000, precond=edd.PC_IDENTITY)
+    assert st["iterations"] < st_id["iterations"]
+    prob.close()
+
+
+@pytest.mark.parametrize("weighted", [0, 1])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_skeleton_operators_parity(dim, weighted):
+    require_gpu()
+    import scipy.sparse.linalg as spla
+    p = _small2d() if dim == 2 else _small3d()
+    prob = make_problem(p)
+    M, L, g = iface.skeleton_matrices(p, lumped=True, weighted=bool(weighted))
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(len(g) * dim)
+    X = x.reshape(-1, dim)
+    yL = to_np(prob.skeleton_op(0, to_cuda(x), weighting=weighted)).reshape(-1, dim)
+    yM = to_np(prob.skeleton_op(1, to_cuda(x), weighting=weighted)).reshape(-1, dim)
+    eL = float(np.linalg.norm(yL - L @ X) / np.linalg.norm(L @ X))
+    eM = float(np.linalg.norm(yM - M @ X) / np.linalg.norm(M @ X))
+    print(f"{dim}D weighted={weighted}: L {eL:.2e} M {eM:.2e}")
+    assert eL <= 1e-13 and eM <= 1e-14
+    yS = to_np(prob.skeleton_op(3, to_cuda(x), weighting=weighted, tol=1e-13,
+                                maxit=2000)).reshape(-1, dim)
+    ref = spla.spsolve(L.tocsc(), X)
+    eS = float(np.linalg.norm(yS - ref) / np.linalg.norm(ref))
+    print(f"  inner PCG {eS:.2e}")
+    assert eS <= 1e-10
+    if not weighted:
+        B = iface.FaceBlockPreconditioner(p, L)
+        yB = to_np(prob.skeleton_op(2, to_cuda(x), weighting=0)).reshape(-1, dim)
+        refB = np.column_stack([B.apply(X[:, c]) for c in range(dim)])
+        eB = float(np.linalg.norm(yB - refB) / np.linalg.norm(refB))
+        print(f"  face blocks {eB:.2e}")
+        assert eB <= 1e-12
+    prob.close()
