@@ -104,10 +104,13 @@ typedef struct edd_solve_opts {
   double theta;       /* H_theta index in [0,1]; < 0 picks the value reported  */
                       /* best for the number of subdomains (0.5 at 4, 0.6 at */
                       /* 16, 0.7 at 64, 0.75 from 256, log-linear between)   */
-  int lanczos_kmax;   /* max inverse-Lanczos steps per application           */
+  int lanczos_kmax;   /* max inverse-Lanczos steps per application (<= 64)   */
   double lanczos_tol; /* relative change that stops Lanczos early            */
   double inner_tol;   /* relative tolerance of the skeleton-Laplacian PCG    */
   int inner_maxit;    /* max iterations of that PCG                          */
+                      /* lanczos_tol <= 0 and inner_tol <= 0 select the     */
+                      /* device-resident form: exactly lanczos_kmax (<= 32) */
+                      /* steps of inner_maxit iterations, no host waits     */
   int use_initial_guess; /* u_dev holds an initial guess on entry             */
   int outer_maxit;    /* mixed mode: max FP64 outer iterations               */
   double mixed_inner_tol; /* mixed mode: interface tolerance of inner solves  */
@@ -146,8 +149,9 @@ typedef struct edd_info {
 } edd_info;
 
 /* Fill *o with the defaults: tol 1e-8, maxit 2000, FP64, Hhat_theta with
- * theta 0.5, kmax 20, lanczos_tol 1e-2, inner_tol 1e-3 (Section 4),
- * inner_maxit 50, no initial guess, outer_maxit 20, mixed_inner_tol 1e-3,
+ * theta 0.5 in the device-resident form with 4 Lanczos steps of 4 inner
+ * iterations (the paper's adaptive form: lanczos_tol 1e-2, inner_tol 1e-3,
+ * Section 4), no initial guess, outer_maxit 20, mixed_inner_tol 1e-3,
  * flexible_window 0, interface_weighting 1. */
 void edd_default_opts(edd_solve_opts *o);
 

@@ -408,10 +408,10 @@ void edd_default_opts(edd_solve_opts *o) {
   o->precision = EDD_MODE_F64;
   o->precond = EDD_PC_HTHETA;
   o->theta = 0.5;
-  o->lanczos_kmax = 20;
-  o->lanczos_tol = 1e-2;
-  o->inner_tol = 1e-3;
-  o->inner_maxit = 50;
+  o->lanczos_kmax = 4;
+  o->lanczos_tol = 0.0;
+  o->inner_tol = 0.0;
+  o->inner_maxit = 4;
   o->use_initial_guess = 0;
   o->outer_maxit = 20;
   o->mixed_inner_tol = 1e-3;

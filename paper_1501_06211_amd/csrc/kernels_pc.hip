@@ -43,7 +43,10 @@ enum : int {
   P_B0 = P_BASE + 21,   // [3] |b|_M^2
   P_BETA = P_BASE + 24, // [3] previous Lanczos beta
   P_H = P_BASE + 32,    // [65*3] reorthogonalisation / combination coefficients
-  P_END = P_H + 65 * 3
+  P_END = P_H + 65 * 3,
+  P_AH = 900,           // [64*3] alpha history (device-resident mode)
+  P_BH = 1100,          // [64*3] beta history
+  P_CO = 1300           // [64*3] final combination coefficients
 };
 
 constexpr int kMaxFace = 512;  // larger faces fall back to the diagonal
@@ -360,6 +363,72 @@ __global__ __launch_bounds__(kBlock) void k_lanczos3(int64_t nG, const double *_
     double v = fma(-scal[P_A + c], qj[i * D + c], w[i * D + c]);
     if (qm) v = fma(-scal[P_BETA + c], qm[i * D + c], v);
     w[i * D + c] = v;
+  }
+}
+
+// history of the Lanczos scalars for step j; beta = sqrt(|w|_M^2)
+__global__ void k_store_ab(double *__restrict__ scal, int j, int D) {
+  const int c = threadIdx.x;
+  if (c >= D) return;
+  const double b = sqrt(fmax(scal[P_B + c], 0.0));
+  scal[P_AH + j * D + c] = scal[P_A + c];
+  scal[P_BH + j * D + c] = b;
+  scal[P_BETA + c] = b;
+}
+
+// coef[i*D+c] = |b|_M * (T^{pw} e1)_i for the k x k tridiagonal of component
+// c, by cyclic Jacobi rotations; one thread per component (k <= 32)
+__global__ void k_lanczos_coef(double *__restrict__ scal, int k, int D, double pw) {
+  __shared__ double A[3][32 * 32];
+  __shared__ double U[3][32 * 32];
+  const int c = threadIdx.x;
+  if (c >= D) return;
+  double *a = A[c], *u = U[c];
+  for (int i = 0; i < k * k; ++i) { a[i] = 0.0; u[i] = 0.0; }
+  for (int i = 0; i < k; ++i) {
+    a[i * k + i] = scal[P_AH + i * D + c];
+    if (i + 1 < k) a[i * k + i + 1] = a[(i + 1) * k + i] = scal[P_BH + i * D + c];
+    u[i * k + i] = 1.0;
+  }
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < k; ++i) {
+      diag += a[i * k + i] * a[i * k + i];
+      for (int j = i + 1; j < k; ++j) off += a[i * k + j] * a[i * k + j];
+    }
+    if (off <= 1e-30 * diag) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = a[p * k + q];
+        if (fabs(apq) < 1e-300) continue;
+        const double tau = (a[q * k + q] - a[p * k + p]) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+        for (int r = 0; r < k; ++r) {
+          const double arp = a[r * k + p], arq = a[r * k + q];
+          a[r * k + p] = cs * arp - sn * arq;
+          a[r * k + q] = sn * arp + cs * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double apr = a[p * k + r], aqr = a[q * k + r];
+          a[p * k + r] = cs * apr - sn * aqr;
+          a[q * k + r] = sn * apr + cs * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double urp = u[r * k + p], urq = u[r * k + q];
+          u[r * k + p] = cs * urp - sn * urq;
+          u[r * k + q] = sn * urp + cs * urq;
+        }
+      }
+  }
+  const double b0 = sqrt(fmax(scal[P_B0 + c], 0.0));
+  for (int i = 0; i < k; ++i) {
+    double y = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double l = fmax(a[j * k + j], 0.0);
+      y += u[i * k + j] * pow(l, pw) * u[0 * k + j];
+    }
+    scal[P_CO + i * D + c] = b0 * y;
   }
 }
 
@@ -746,7 +815,8 @@ struct PC {
                                              x, y);
   }
 
-  // y ~ L^{-1} b (all components), relative tolerance tol; returns its or <0
+  // y ~ L^{-1} b (all components), relative tolerance tol; with tol <= 0
+  // exactly maxit iterations run with no host synchronisation
   int inner_pcg(const double *b, double *y, double tol, int maxit, int *its_out) {
     double *r = p->pc_v_d[3], *z = p->pc_v_d[4], *pv = p->pc_v_d[5], *q = p->pc_v_d[6];
     launch_fill(p, nG * D, 0.0, y);
@@ -760,14 +830,19 @@ struct PC {
       cdots(1, pv, q, nullptr, nullptr, nullptr, P_PQ, 0);
       k_pcg_update<D><<<g1, kBlock, 0, p->stream>>>(nG, p->scal_d, y, pv, r, q);
       face_precond(r, z);
-      cdots(2, r, z, r, r, nullptr, P_RZN, P_RR);
-      int rc = read_scalars(p, P_RZ, 15);
-      if (rc) return rc;
-      const double *s = p->scal_h;
-      bool done = true;
-      for (int c = 0; c < D; ++c)
-        if (s[P_RR + c] > tol * tol * s[P_BB + c]) done = false;
-      if (done) { ++it; break; }
+      if (tol > 0.0) {
+        cdots(2, r, z, r, r, nullptr, P_RZN, P_RR);
+        int rc = read_scalars(p, P_RZ, 15);
+        if (rc) return rc;
+        const double *s = p->scal_h;
+        bool done = true;
+        for (int c = 0; c < D; ++c)
+          if (s[P_RR + c] > tol * tol * s[P_BB + c]) done = false;
+        if (done) { ++it; break; }
+      } else {
+        if (it + 1 == maxit) { ++it; break; }
+        cdots(1, r, z, nullptr, nullptr, nullptr, P_RZN, 0);
+      }
       k_pcg_dir<D><<<g1, kBlock, 0, p->stream>>>(nG, p->scal_d, z, pv);
       k_copy_scal<<<1, 64, 0, p->stream>>>(p->scal_d, P_RZ, P_RZN, D);
     }
@@ -833,9 +908,61 @@ void tridiag_power(int k, const double *alpha, const double *beta, double pw,
   }
 }
 
+// Fixed number of Lanczos steps and inner iterations; every scalar stays on
+// the device (no host synchronisation), so the whole application is one
+// asynchronous stream of kernels.
+template <int D>
+int apply_device(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
+                 edd_solve_stats *st) {
+  const int64_t nG = p->n_gamma;
+  PC<D> pc{p, nG, (unsigned)((nG + kBlock - 1) / kBlock)};
+  const double theta = o->theta >= 0.0 ? o->theta : p->theta_default;
+  const int k = std::min(o->lanczos_kmax, 32);
+  if (p->pc_kcap < k + 1) {
+    double *Q = (double *)dev_alloc(p, sizeof(double) * nG * D * (k + 1));
+    if (!Q) return EDD_ENOMEM;
+    p->pc_Q_d = Q;
+    p->pc_kcap = k + 1;
+  }
+  const int64_t n = nG * D;
+  double *Q = p->pc_Q_d;
+  double *w = p->pc_v_d[0], *t = p->pc_v_d[1];
+  k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, 0, 3, p->skM_d, r, t);
+  pc.cdots(1, t, t, nullptr, nullptr, p->skM_d, P_B0, 0);
+  k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_B0, 1, nullptr, t, Q);
+  for (int j = 0; j < k; ++j) {
+    double *qj = Q + (int64_t)j * n;
+    k_dscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->skM_d, qj, t);
+    int its = 0;
+    int rc = pc.inner_pcg(t, w, 0.0, o->inner_maxit, &its);
+    if (rc) return rc;
+    if (st) st->inner_iterations += its;
+    pc.cdots(1, qj, w, nullptr, nullptr, p->skM_d, P_A, 0);
+    k_lanczos3<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, qj,
+                                                   j > 0 ? Q + (int64_t)(j - 1) * n : nullptr, w);
+    unsigned g = grid_for(nG);
+    if (g > 128) g = 128;
+    k_cwindow_dots<D><<<g, kBlock, 0, p->stream>>>(nG, j + 1, Q, w, p->skM_d, p->partials_d);
+    k_reduce<<<(j + 1) * D, kBlock, 0, p->stream>>>(p->partials_d, (int)g, (j + 1) * D,
+                                                    p->scal_d + P_H);
+    k_ccombine<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, j + 1, Q, p->scal_d + P_H, 1.0, -1.0, w);
+    pc.cdots(1, w, w, nullptr, nullptr, p->skM_d, P_B, 0);
+    k_store_ab<<<1, 64, 0, p->stream>>>(p->scal_d, j, D);
+    if (j + 1 < k)
+      k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_B, 1, nullptr, w,
+                                                   Q + (int64_t)(j + 1) * n);
+    if (st) st->lanczos_steps++;
+  }
+  k_lanczos_coef<<<1, 64, 0, p->stream>>>(p->scal_d, k, D, 1.0 - theta);
+  k_ccombine<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, k, Q, p->scal_d + P_CO, 0.0, 1.0, z);
+  if (st) st->precond_applications++;
+  return hipGetLastError() == hipSuccess ? EDD_OK : EDD_EHIP;
+}
+
 template <int D>
 int apply_t(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
             edd_solve_stats *st) {
+  if (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0) return apply_device<D>(p, r, z, o, st);
   const int64_t nG = p->n_gamma;
   PC<D> pc{p, nG, (unsigned)((nG + kBlock - 1) / kBlock)};
   const double theta = o->theta >= 0.0 ? o->theta : p->theta_default;
