@@ -63,8 +63,8 @@ extern "C" {
 #define EDD_CLAMP_Z1 32
 
 #define EDD_MODE_F64 0   /* everything in FP64                               */
-#define EDD_MODE_MIXED 1 /* FP64 outer Krylov on K; inner Schur solves with  */
-                         /* FP32 interior factors and an FP32 preconditioner */
+#define EDD_MODE_MIXED 1 /* iterative refinement of the interface problem:   */
+                         /* FP64 residuals, inner solves with FP32 factors  */
 
 #define EDD_PC_IDENTITY 0 /* S~ = I                                           */
 #define EDD_PC_HTHETA 1   /* S~ = Hhat_theta by inverse Lanczos (Section 3)   */
@@ -112,8 +112,9 @@ typedef struct edd_solve_opts {
                       /* device-resident form: exactly lanczos_kmax (<= 32) */
                       /* steps of inner_maxit iterations, no host waits     */
   int use_initial_guess; /* u_dev holds an initial guess on entry             */
-  int outer_maxit;    /* mixed mode: max FP64 outer iterations               */
-  double mixed_inner_tol; /* mixed mode: interface tolerance of inner solves  */
+  int outer_maxit;    /* mixed mode: max refinement rounds                   */
+  double mixed_inner_tol; /* mixed mode: relative tolerance of each round's   */
+                          /* FP32-factor interface solve                      */
   int flexible_window; /* directions kept by the flexible Krylov (0 = all,   */
                        /* capped at 256; 1 = short recurrence)               */
   int interface_weighting; /* 0: M, L of the skeleton as in the paper;        */
@@ -124,7 +125,7 @@ typedef struct edd_solve_opts {
 typedef struct edd_solve_stats {
   int status;
   int iterations;           /* interface Krylov iterations (all inner solves) */
-  int outer_iterations;     /* FP64 outer iterations (mixed mode), else 0     */
+  int outer_iterations;     /* refinement rounds (mixed mode), else 0         */
   int precond_applications;
   int lanczos_steps;        /* total inverse-Lanczos steps                    */
   int inner_iterations;     /* total skeleton-Laplacian PCG iterations        */
@@ -151,7 +152,7 @@ typedef struct edd_info {
 /* Fill *o with the defaults: tol 1e-8, maxit 2000, FP64, Hhat_theta with
  * theta 0.5 in the device-resident form with 4 Lanczos steps of 4 inner
  * iterations (the paper's adaptive form: lanczos_tol 1e-2, inner_tol 1e-3,
- * Section 4), no initial guess, outer_maxit 20, mixed_inner_tol 1e-3,
+ * Section 4), no initial guess, outer_maxit 20, mixed_inner_tol 1e-4,
  * flexible_window 0, interface_weighting 1. */
 void edd_default_opts(edd_solve_opts *o);
 

@@ -11,10 +11,8 @@
 // final FP64 residual ||f - K u|| is recomputed with the element kernel and
 // the iteration resumes if it is above the tolerance.
 //
-// Mixed mode (the inexact right preconditioner of Section 3): an FP64
-// flexible CG on the full system K u = f whose preconditioner is the whole
-// interface solve above run with FP32 interior factors and a loose
-// interface tolerance.
+// Mixed mode: iterative refinement on the interface problem, the inner
+// interface solves using FP32 interior factors (see solve_mixed).
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -164,31 +162,43 @@ static void window_orthogonalise(edd_problem *p, int64_t n, double *ringP,
   }
 }
 
-// Interface solve of K u = f (eq. (3MatSplit)) with interior factors of
-// precision prec.  Stops when ||r_G|| <= tol_abs.  Returns EDD_OK,
-// EDD_NOT_CONVERGED or an error; *iters receives the interface iterations.
-static int schur_solve_core(edd_problem *p, const double *f, double *u, int prec,
-                            double tol_abs, bool use_guess,
-                            const edd_solve_opts *o, edd_solve_stats *st,
-                            int maxit, int window, int *iters) {
-  const int D = p->g.dim;
-  const int64_t nG = p->n_gamma * D;
-  double *x = p->w_G[0], *r = p->w_G[1], *z = p->w_G[2], *g = p->w_G[3],
-         *tmp = p->w_G[4];
-  *iters = 0;
-  // condensation
+// Condensation g = f_G - K_GI K_II^{-1} f_I (first two lines of eq.
+// (3MatSplit)) with interior factors of precision prec.
+static void condense(edd_problem *p, const double *f, double *g, int prec) {
   double *wI = p->w_I[0];
   launch_gather(p, p->inode_d, p->n_inodes, f, wI);
   launch_band_solve(p, prec, wI, wI);
   launch_apply_mapped(p, p->gnode_d, p->n_gamma, wI, 1.0, nullptr, 0.0, f, -1.0, g);
+}
+
+// Back-substitution u_I = K_II^{-1} (f_I - K_IG u_G) (third line of eq.
+// (3MatSplit)) and assembly of the full-length u.
+static void back_substitute(edd_problem *p, const double *f, const double *uG, double *u,
+                            int prec) {
+  double *t = p->w_I[1];
+  launch_apply_mapped(p, p->inode_d, p->n_inodes, nullptr, 0.0, uG, 1.0, f, -1.0, t);
+  launch_band_solve(p, prec, t, t);
+  launch_scatter_solution(p, t, uG, u);
+}
+
+// Flexible CG on S x = rhs with S applied through interior factors of
+// precision prec; x holds the initial guess when use_guess.  Stops when the
+// recursive residual is <= tol_abs.  Returns EDD_OK, EDD_NOT_CONVERGED,
+// EDD_EBREAKDOWN or an error; *iters receives the iterations.
+static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
+                         double tol_abs, bool use_guess, const edd_solve_opts *o,
+                         edd_solve_stats *st, int maxit, int window, int *iters) {
+  const int D = p->g.dim;
+  const int64_t nG = p->n_gamma * D;
+  double *r = p->w_G[1], *z = p->w_G[2], *tmp = p->w_G[4];
+  *iters = 0;
   if (use_guess) {
-    launch_gather(p, p->gnode_d, p->n_gamma, u, x);
     apply_S(p, x, tmp, prec);
-    launch_copy(p, nG, g, r);
+    launch_copy(p, nG, rhs, r);
     launch_axpby(p, nG, -1.0, tmp, 1.0, r);
   } else {
     launch_fill(p, nG, 0.0, x);
-    launch_copy(p, nG, g, r);
+    launch_copy(p, nG, rhs, r);
   }
   {
     const double *a[1] = {r}, *b[1] = {r};
@@ -234,12 +244,21 @@ static int schur_solve_core(edd_problem *p, const double *f, double *u, int prec
     }
   }
   *iters = k;
-  if (status == EDD_EBREAKDOWN) return status;
-  // back-substitution
-  double *t = p->w_I[1];
-  launch_apply_mapped(p, p->inode_d, p->n_inodes, nullptr, 0.0, x, 1.0, f, -1.0, t);
-  launch_band_solve(p, prec, t, t);
-  launch_scatter_solution(p, t, x, u);
+  return status;
+}
+
+// The three steps of eq. (3MatSplit) with interior factors of precision
+// prec: condensation, interface FCG to tol_abs, back-substitution.
+static int schur_solve_core(edd_problem *p, const double *f, double *u, int prec,
+                            double tol_abs, bool use_guess, const edd_solve_opts *o,
+                            edd_solve_stats *st, int maxit, int window, int *iters) {
+  double *x = p->w_G[0], *g = p->w_G[3];
+  condense(p, f, g, prec);
+  if (use_guess) launch_gather(p, p->gnode_d, p->n_gamma, u, x);
+  const int status = interface_fcg(p, g, x, prec, tol_abs, use_guess, o, st, maxit,
+                                   window, iters);
+  if (status == EDD_EBREAKDOWN || status < 0) return status;
+  back_substitute(p, f, x, u, prec);
   return status;
 }
 
@@ -290,107 +309,66 @@ static int solve_plain(edd_problem *p, const double *f, double *u,
   return status;
 }
 
-struct OuterBuffers {
-  double *r, *z, *P, *Q;
-  int cap;
-};
-
-static int ensure_outer(edd_problem *p, int cap, OuterBuffers *ob) {
-  const size_t nd = (size_t)p->ndof;
-  const size_t need = nd * (2 + 2 * (size_t)cap);
-  if (p->outer_len < need) {
-    double *buf = (double *)dev_alloc(p, sizeof(double) * need);
-    if (!buf) return EDD_ENOMEM;
-    p->outer_d = buf;
-    p->outer_len = need;
-  }
-  ob->r = p->outer_d;
-  ob->z = p->outer_d + nd;
-  ob->P = p->outer_d + 2 * nd;
-  ob->Q = p->outer_d + 2 * nd + nd * cap;
-  ob->cap = cap;
-  return EDD_OK;
-}
-
+// Mixed precision (Section 3's inexact interface solves, realised as
+// iterative refinement): FP64 condensation; rounds of
+//   r = g - S x        with the FP64 interior factors,
+//   S d = r            by FCG with the FP32 interior factors, to a loose
+//                      relative tolerance (mixed_inner_tol),
+//   x += d;
+// then FP64 back-substitution and the FP64 true residual.  A round that
+// does not halve the interface residual ends the reduced-precision phase and
+// the FP64 solve finishes from the current iterate.
 static int solve_mixed(edd_problem *p, const double *f, double *u,
                        const edd_solve_opts *o, edd_solve_stats *st, double nf) {
-  const int64_t n = p->ndof;
-  const int cap = std::max(1, std::min(o->outer_maxit, 64));
-  OuterBuffers ob{};
-  int rc = ensure_outer(p, cap, &ob);
-  if (rc) return rc;
-  const int inner_window = o->flexible_window > 0
-                               ? o->flexible_window
-                               : (o->precond == EDD_PC_IDENTITY ? 1 : 256);
-  // r = f - K u
-  if (o->use_initial_guess) {
-    launch_apply_full(p, u, p->w_full[0]);
-    launch_copy(p, n, f, ob.r);
-    launch_axpby(p, n, -1.0, p->w_full[0], 1.0, ob.r);
-  } else {
-    launch_fill(p, n, 0.0, u);
-    launch_copy(p, n, f, ob.r);
-  }
-  launch_mask_dirichlet(p, ob.r);
+  const int D = p->g.dim;
+  const int64_t nG = p->n_gamma * D;
+  double *g = p->w_G[3], *x = p->w_G[5], *d = p->w_G[0], *r = p->w_G[6],
+         *t = p->w_G[7];
+  const int window = o->flexible_window > 0
+                         ? o->flexible_window
+                         : (o->precond == EDD_PC_IDENTITY ? 1 : 256);
+  condense(p, f, g, EDD_F64);
+  if (o->use_initial_guess) launch_gather(p, p->gnode_d, p->n_gamma, u, x);
+  else launch_fill(p, nG, 0.0, x);
   const double tol_abs = o->tol * nf;
-  double rnorm = 0.0;
-  {
-    const double *a[1] = {ob.r}, *b[1] = {ob.r};
-    launch_dots(p, n, 1, a, b, S_RR);
-    rc = read_scalars(p, S_RR, 1);
-    if (rc) return rc;
-    rnorm = std::sqrt(p->scal_h[S_RR]);
-  }
-  int k = 0;
-  int status = EDD_OK;
-  double prev = rnorm;
-  int stall = 0;
-  while (rnorm > tol_abs) {
-    if (k >= o->outer_maxit) { status = EDD_NOT_CONVERGED; break; }
-    int its = 0;
-    // inner interface solve of K z = r in reduced precision
-    int irc = schur_solve_core(p, ob.r, ob.z, EDD_F32, o->mixed_inner_tol * rnorm,
-                               false, o, st, o->maxit, inner_window, &its);
-    st->iterations += its;
-    if (irc < 0 && irc != EDD_EBREAKDOWN) return irc;
-    const int slot = k % cap;
-    double *Pk = ob.P + (int64_t)slot * n;
-    double *Qk = ob.Q + (int64_t)slot * n;
-    window_orthogonalise(p, n, ob.P, ob.Q, cap, k, std::min(k, cap), ob.z, Pk,
-                         S_C_BASE, S_PQ_BASE);
-    launch_apply_full(p, Pk, Qk);
+  double prev = -1.0;
+  int status = EDD_NOT_CONVERGED;
+  int round = 0;
+  for (; round < std::max(1, o->outer_maxit); ++round) {
+    // FP64 interface residual
+    apply_S(p, x, t, EDD_F64);
+    launch_copy(p, nG, g, r);
+    launch_axpby(p, nG, -1.0, t, 1.0, r);
     {
-      const double *a[2] = {Pk, Pk}, *b[2] = {Qk, ob.r};
-      launch_dots(p, n, 2, a, b, S_PQCUR);
+      const double *a[1] = {r}, *b[1] = {r};
+      launch_dots(p, nG, 1, a, b, S_RES);
     }
-    launch_cg_update(p, n, S_PR, S_PQCUR, u, Pk, ob.r, Qk, S_RR, S_PQ_BASE + slot);
-    rc = read_scalars(p, S_RR, 4);
+    int rc = read_scalars(p, S_RES, 1);
     if (rc) return rc;
-    ++k;
-    rnorm = std::sqrt(p->scal_h[S_RR]);
-    if (!(p->scal_h[S_PQCUR] > 0.0) || !std::isfinite(rnorm)) {
-      status = EDD_EBREAKDOWN;
-      break;
-    }
-    stall = (rnorm > 0.5 * prev) ? stall + 1 : 0;
-    prev = rnorm;
-    if (stall >= 2) { status = EDD_NOT_CONVERGED; break; }
+    const double rn = std::sqrt(p->scal_h[S_RES]);
+    if (!std::isfinite(rn)) return EDD_EBREAKDOWN;
+    if (rn <= 0.5 * tol_abs) { status = EDD_OK; break; }
+    if (prev >= 0.0 && rn > 0.5 * prev) break;  // stalled
+    prev = rn;
+    int its = 0;
+    rc = interface_fcg(p, r, d, EDD_F32, std::max(o->mixed_inner_tol * rn, 0.25 * tol_abs),
+                       false, o, st, o->maxit - st->iterations, window, &its);
+    st->iterations += its;
+    if (rc < 0) return rc;
+    launch_axpby(p, nG, 1.0, d, 1.0, x);
+    if (st->iterations >= o->maxit) break;
   }
-  st->outer_iterations = k;
+  st->outer_iterations = round;
+  back_substitute(p, f, x, u, EDD_F64);
   double rel = 0.0;
-  rc = true_residual(p, f, u, &rel);
+  int rc = true_residual(p, f, u, &rel);
   if (rc) return rc;
   st->rel_residual = rel;
-  if (rel > o->tol) {
-    // the reduced-precision path did not reach the tolerance: finish with
-    // the FP64 interface solve started from the current iterate
-    st->flags |= EDD_FLAG_MIXED_FALLBACK;
-    edd_solve_opts o2 = *o;
-    o2.use_initial_guess = 1;
-    return solve_plain(p, f, u, &o2, st, nf);
-  }
-  (void)status;
-  return EDD_OK;
+  if (rel <= o->tol) return EDD_OK;
+  st->flags |= EDD_FLAG_MIXED_FALLBACK;
+  edd_solve_opts o2 = *o;
+  o2.use_initial_guess = 1;
+  return solve_plain(p, f, u, &o2, st, nf);
 }
 
 }  // namespace edd
@@ -414,7 +392,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->inner_maxit = 4;
   o->use_initial_guess = 0;
   o->outer_maxit = 20;
-  o->mixed_inner_tol = 1e-3;
+  o->mixed_inner_tol = 1e-4;
   o->flexible_window = 0;
   o->interface_weighting = 1;
 }

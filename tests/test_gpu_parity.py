@@ -132,3 +132,27 @@ def test_error_paths():
     u0, st0 = prob.solve(torch.zeros_like(f), precond=edd.PC_IDENTITY)
     assert float(u0.abs().max()) == 0.0
     prob.close()
+
+
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_mixed_precision_solve(name):
+    """Interface refinement with FP32 interior factors: the FP64 true
+    residual reaches the tolerance and the answer matches the oracle; the
+    FP32-only error of one interface solve is reported."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    wk = CASES[name]
+    prob = make_problem(wk)
+    uref = fe.solve_direct(wk)
+    cref = fe.compliance(wk.f, uref)
+    u, st = prob.solve(to_cuda(wk.f), tol=1e-11, maxit=4000, precision=edd.MODE_MIXED,
+                       precond=edd.PC_HTHETA)
+    un = to_np(u)
+    err = float(np.linalg.norm(un - uref) / np.linalg.norm(uref))
+    cerr = abs(st["compliance"] - cref) / abs(cref)
+    print(f"{name} mixed: its={st['iterations']} rounds={st['outer_iterations']} "
+          f"flags={st['flags']} res={st['rel_residual']:.2e} u_err={err:.2e} c_err={cerr:.2e}")
+    assert st["rel_residual"] <= 1e-11
+    assert err <= 1e-8 and cerr <= 1e-10
+    assert st["flags"] & edd.FLAG_MIXED_FALLBACK == 0
+    prob.close()
