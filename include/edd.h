@@ -65,6 +65,10 @@ extern "C" {
 #define EDD_MODE_F64 0   /* everything in FP64                               */
 #define EDD_MODE_MIXED 1 /* iterative refinement of the interface problem:   */
                          /* FP64 residuals, inner solves with FP32 factors  */
+#define EDD_MODE_RELAXED 2 /* one flexible CG whose S applies switch from    */
+                           /* FP64 to FP32 factors once the residual is     */
+                           /* below mixed_inner_tol times the initial one   */
+                           /* (inexact Krylov with relaxed accuracy)        */
 
 #define EDD_PC_IDENTITY 0 /* S~ = I                                           */
 #define EDD_PC_HTHETA 1   /* S~ = Hhat_theta by inverse Lanczos (Section 3)   */
@@ -113,8 +117,10 @@ typedef struct edd_solve_opts {
                       /* steps of inner_maxit iterations, no host waits     */
   int use_initial_guess; /* u_dev holds an initial guess on entry             */
   int outer_maxit;    /* mixed mode: max refinement rounds                   */
-  double mixed_inner_tol; /* mixed mode: relative tolerance of each round's   */
-                          /* FP32-factor interface solve                      */
+  double mixed_inner_tol; /* EDD_MODE_MIXED: relative tolerance of each      */
+                          /* round's FP32-factor interface solve;            */
+                          /* EDD_MODE_RELAXED: relative residual at which    */
+                          /* the S applies switch to FP32 factors            */
   int flexible_window; /* directions kept by the flexible Krylov (0 = all,   */
                        /* capped at 256; 1 = short recurrence)               */
   int interface_weighting; /* 0: M, L of the skeleton as in the paper;        */
@@ -227,13 +233,15 @@ int edd_get_gamma_nodes(edd_problem *p, int32_t *nodes_host);
 int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host);
 
 /* ---- kernel timing ----------------------------------------------------- */
-#define EDD_KT_BAND_SOLVE 0    /* batched forward+backward substitution    */
+#define EDD_KT_BAND_SOLVE 0    /* batched forward+backward substitution,   */
+                               /* FP64 factors                             */
 #define EDD_KT_BAND_CHOLESKY 1 /* batched band Cholesky                    */
 #define EDD_KT_APPLY_K 2       /* full matrix-free K apply                 */
 #define EDD_KT_APPLY_MAPPED 3  /* K apply restricted to interior/interface */
 #define EDD_KT_ASSEMBLE 4      /* band assembly of K_II                    */
 #define EDD_KT_PRECOND 5       /* interface preconditioner kernels         */
 #define EDD_KT_LAYOUTS 6       /* solve layouts of the interior factors    */
+#define EDD_KT_BAND_SOLVE32 7  /* the substitutions with FP32 factors      */
 #define EDD_KT_COUNT 8
 
 typedef struct edd_kernel_times {

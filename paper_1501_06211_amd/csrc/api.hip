@@ -187,7 +187,8 @@ static void back_substitute(edd_problem *p, const double *f, const double *uG, d
 // EDD_EBREAKDOWN or an error; *iters receives the iterations.
 static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
                          double tol_abs, bool use_guess, const edd_solve_opts *o,
-                         edd_solve_stats *st, int maxit, int window, int *iters) {
+                         edd_solve_stats *st, int maxit, int window, int *iters,
+                         double relax_abs = -1.0) {
   const int D = p->g.dim;
   const int64_t nG = p->n_gamma * D;
   double *r = p->w_G[1], *z = p->w_G[2], *tmp = p->w_G[4];
@@ -216,6 +217,9 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   int k = 0;
   while (std::sqrt(rr) > tol_abs) {
     if (k >= maxit) { status = EDD_NOT_CONVERGED; break; }
+    // relaxed operator accuracy: once the residual is small, the S applies
+    // may carry a larger error without spoiling the attainable accuracy
+    if (relax_abs > 0.0 && std::sqrt(rr) <= relax_abs) prec = EDD_F32;
     const double *zp = r;
     if (!pc_identity) {
       rc = precond_apply(p, r, z, o, st, prec == EDD_F32);
@@ -366,6 +370,59 @@ static int solve_mixed(edd_problem *p, const double *f, double *u,
   st->rel_residual = rel;
   if (rel <= o->tol) return EDD_OK;
   st->flags |= EDD_FLAG_MIXED_FALLBACK;
+  edd_solve_opts o2 = *o;
+  o2.use_initial_guess = 1;
+  return solve_plain(p, f, u, &o2, st, nf);
+}
+
+// Relaxed mixed precision (inexact Krylov): one FCG on S with FP64 interior
+// factors until the interface residual falls below mixed_inner_tol times the
+// initial one, FP32-stored factors after that; FP64 condensation,
+// back-substitution and true residual.  If the true residual misses the
+// tolerance the FP64 solve restarts from the current iterate.
+static int solve_relaxed(edd_problem *p, const double *f, double *u,
+                         const edd_solve_opts *o, edd_solve_stats *st, double nf) {
+  const int D = p->g.dim;
+  const int64_t nG = p->n_gamma * D;
+  double *x = p->w_G[0], *g = p->w_G[3];
+  const int window = o->flexible_window > 0
+                         ? o->flexible_window
+                         : (o->precond == EDD_PC_IDENTITY ? 1 : 256);
+  condense(p, f, g, EDD_F64);
+  const bool guess = o->use_initial_guess != 0;
+  if (guess) launch_gather(p, p->gnode_d, p->n_gamma, u, x);
+  // initial interface residual norm sets the switch point
+  {
+    double *t = p->w_G[4], *r = p->w_G[1];
+    if (guess) {
+      apply_S(p, x, t, EDD_F64);
+      launch_copy(p, nG, g, r);
+      launch_axpby(p, nG, -1.0, t, 1.0, r);
+    } else {
+      launch_copy(p, nG, g, r);
+    }
+    const double *a[1] = {r}, *b[1] = {r};
+    launch_dots(p, nG, 1, a, b, S_RES);
+  }
+  int rc = read_scalars(p, S_RES, 1);
+  if (rc) return rc;
+  const double r0 = std::sqrt(p->scal_h[S_RES]);
+  const double tol_abs = o->tol * nf;
+  int its = 0;
+  int status = interface_fcg(p, g, x, EDD_F64, tol_abs, guess, o, st, o->maxit, window,
+                             &its, o->mixed_inner_tol * r0);
+  st->iterations += its;
+  if (status == EDD_EBREAKDOWN || status < 0) return status;
+  back_substitute(p, f, x, u, EDD_F64);
+  double rel = 0.0;
+  rc = true_residual(p, f, u, &rel);
+  if (rc) return rc;
+  st->rel_residual = rel;
+  st->outer_iterations = 1;
+  if (rel <= o->tol) return EDD_OK;
+  if (status == EDD_NOT_CONVERGED) return status;
+  // the recursive residual drifted under the relaxed applies: FP64 restart
+  st->flags |= EDD_FLAG_TRUE_RES_RESTART;
   edd_solve_opts o2 = *o;
   o2.use_initial_guess = 1;
   return solve_plain(p, f, u, &o2, st, nf);
@@ -689,8 +746,10 @@ int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
   if (o.precond == EDD_PC_HTHETA &&
       (o.lanczos_kmax < 1 || o.lanczos_kmax > 64 || o.inner_maxit < 1 || o.theta > 1.0))
     return EDD_EINVAL;
-  if (o.precision != EDD_MODE_F64 && o.precision != EDD_MODE_MIXED) return EDD_EINVAL;
-  if (o.precision == EDD_MODE_MIXED && !(p->factor_precision & EDD_F32)) return EDD_ESTATE;
+  if (o.precision != EDD_MODE_F64 && o.precision != EDD_MODE_MIXED &&
+      o.precision != EDD_MODE_RELAXED)
+    return EDD_EINVAL;
+  if (o.precision != EDD_MODE_F64 && !(p->factor_precision & EDD_F32)) return EDD_ESTATE;
   if (!(p->factor_precision & EDD_F64)) return EDD_ESTATE;
   edd_solve_stats st{};
   const auto t0 = std::chrono::steady_clock::now();
@@ -703,8 +762,10 @@ int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
     launch_fill(p, p->ndof, 0.0, u_dev);
   } else if (o.precision == EDD_MODE_F64) {
     status = solve_plain(p, f_dev, u_dev, &o, &st, nf);
-  } else {
+  } else if (o.precision == EDD_MODE_MIXED) {
     status = solve_mixed(p, f_dev, u_dev, &o, &st, nf);
+  } else {
+    status = solve_relaxed(p, f_dev, u_dev, &o, &st, nf);
   }
   if (status >= 0) {
     const double *a[1] = {f_dev}, *b[1] = {u_dev};

@@ -399,7 +399,7 @@ void launch_band_layouts(edd_problem *p) {
 
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x) {
-  KTimer kt(p, EDD_KT_BAND_SOLVE);
+  KTimer kt(p, precision == EDD_F32 ? EDD_KT_BAND_SOLVE32 : EDD_KT_BAND_SOLVE);
   const bool big = p->max_kd > 64;
   if (precision == EDD_F32) {
     // FP32 factor entries, FP64 right-hand side and accumulation: the error

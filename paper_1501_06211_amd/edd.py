@@ -20,7 +20,7 @@ OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EHIP, ESTATE, ENOTSPD, EBREAKDOWN = -1, -2, -3, -4, -5, -6
 F64, F32 = 1, 2
 CLAMP_X0, CLAMP_X1, CLAMP_Y0, CLAMP_Y1, CLAMP_Z0, CLAMP_Z1 = 1, 2, 4, 8, 16, 32
-MODE_F64, MODE_MIXED = 0, 1
+MODE_F64, MODE_MIXED, MODE_RELAXED = 0, 1, 2
 PC_IDENTITY, PC_HTHETA = 0, 1
 FLAG_TRUE_RES_RESTART, FLAG_MIXED_FALLBACK, FLAG_PC_DROPPED = 1, 2, 4
 
@@ -33,7 +33,7 @@ EXPORTS = [
     "edd_apply_skeleton_op",
 ]
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
-            "precond", "layouts"]
+            "precond", "layouts", "band_solve32"]
 
 
 class EddError(RuntimeError):

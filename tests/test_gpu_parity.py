@@ -134,25 +134,28 @@ def test_error_paths():
     prob.close()
 
 
+@pytest.mark.parametrize("mode", ["mixed", "relaxed"])
 @pytest.mark.parametrize("name", ["2d", "3d"])
-def test_mixed_precision_solve(name):
-    """Interface refinement with FP32 interior factors: the FP64 true
-    residual reaches the tolerance and the answer matches the oracle; the
-    FP32-only error of one interface solve is reported."""
+def test_mixed_precision_solve(name, mode):
+    """Reduced-precision interior factors (interface refinement, or one
+    flexible CG with relaxed operator accuracy): the FP64 true residual
+    reaches the tolerance and the answer matches the oracle."""
     require_gpu()
     from paper_1501_06211_amd import edd
     wk = CASES[name]
     prob = make_problem(wk)
     uref = fe.solve_direct(wk)
     cref = fe.compliance(wk.f, uref)
-    u, st = prob.solve(to_cuda(wk.f), tol=1e-11, maxit=4000, precision=edd.MODE_MIXED,
-                       precond=edd.PC_HTHETA)
+    m = edd.MODE_MIXED if mode == "mixed" else edd.MODE_RELAXED
+    u, st = prob.solve(to_cuda(wk.f), tol=1e-11, maxit=4000, precision=m,
+                       precond=edd.PC_HTHETA, mixed_inner_tol=1e-4)
     un = to_np(u)
     err = float(np.linalg.norm(un - uref) / np.linalg.norm(uref))
     cerr = abs(st["compliance"] - cref) / abs(cref)
-    print(f"{name} mixed: its={st['iterations']} rounds={st['outer_iterations']} "
+    print(f"{name} {mode}: its={st['iterations']} rounds={st['outer_iterations']} "
           f"flags={st['flags']} res={st['rel_residual']:.2e} u_err={err:.2e} c_err={cerr:.2e}")
     assert st["rel_residual"] <= 1e-11
     assert err <= 1e-8 and cerr <= 1e-10
-    assert st["flags"] & edd.FLAG_MIXED_FALLBACK == 0
+    if mode == "mixed":
+        assert st["flags"] & edd.FLAG_MIXED_FALLBACK == 0
     prob.close()
