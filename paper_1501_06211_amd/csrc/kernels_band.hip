@@ -344,6 +344,216 @@ __global__ __launch_bounds__(NT) void k_band_solve(
   for (int i = tid; i < n; i += NT) x[s.dof_off + i] = (double)xs[i];
 }
 
+// ---------------------------------------------------------------------------
+// Substitution for wide bands (kd <= kWideRows), 1024 threads per subdomain.
+// Wavefront 0 works only on the diagonal blocks (the serial chain, as
+// above).  Wavefronts 1..15 own one off-diagonal row each per 64-column
+// block step: forward rows j0+64+t, backward rows j0-kd+t, t < kd.  Each
+// thread issues the factor loads of its next block step as soon as its
+// current step's arithmetic is done, before the barrier that waits for the
+// chain, so the factor stream overlaps the chain instead of following it.
+// Loads come in chunks of CW columns (register budget at 1024 threads); each
+// column's address is wave-uniform plus a per-lane offset.
+// ---------------------------------------------------------------------------
+constexpr int kWideNT = 1024;
+constexpr int kWideRows = kWideNT - 64;
+
+// Factor loads go through a buffer resource whose base sits kWideFront
+// entries before the subdomain's band, so that every offset is a
+// non-negative 32-bit byte count: a per-lane offset shared by all columns
+// plus a wave-uniform column offset (soffset).  Offsets stay inside the
+// padded band storage by construction; the record count (the storage from
+// the base to the end, capped at 4 GiB) makes any stray offset read zero.
+constexpr int kWideFront = 64;
+
+template <typename T>
+__device__ inline T bload(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ inline double bload<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ inline float bload<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// buf[cc] = band entry at element offset e + (c0 + cc) * colstride from the
+// subdomain base (e may be negative down to -kWideFront)
+template <typename T, int CW>
+__device__ inline void load_cols(T (&buf)[CW], __amdgpu_buffer_rsrc_t r, int64_t e,
+                                 int colstride, int c0) {
+  const int voff = (int)((e + kWideFront) * (int64_t)sizeof(T));
+#pragma unroll
+  for (int cc = 0; cc < CW; ++cc)
+    buf[cc] = bload<T>(r, voff, (c0 + cc) * colstride * (int)sizeof(T));
+}
+
+template <typename T>
+__device__ inline __amdgpu_buffer_rsrc_t band_rsrc(const T *base, int64_t entries_to_end) {
+  const int64_t bytes = (entries_to_end + kWideFront) * (int64_t)sizeof(T);
+  const int nrec = bytes > 0x7fffffffll ? 0x7fffffff : (int)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(base - kWideFront), (short)0, nrec,
+                                           0x00020000);
+}
+
+template <typename T, typename W, int CW>
+__global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
+    const SubDesc *__restrict__ subs, const int *__restrict__ order,
+    const T *__restrict__ Cs, const T *__restrict__ Rs, int64_t fac_len,
+    const double *__restrict__ b, double *__restrict__ x) {
+  constexpr int NB = 64, NCH = NB / CW;
+  static_assert(NB % CW == 0, "chunks tile the block");
+  extern __shared__ __align__(16) unsigned char smem[];
+  W *xs = reinterpret_cast<W *>(smem);
+  const SubDesc s = subs[order[blockIdx.x]];
+  const int n = s.n, np = s.np, kd = s.kd, ld = kd + 1;
+  const __amdgpu_buffer_rsrc_t Cr = band_rsrc(Cs + s.fac_off, fac_len - s.fac_off);
+  const __amdgpu_buffer_rsrc_t Rr = band_rsrc(Rs + s.fac_off, fac_len - s.fac_off);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const bool chainw = tid < 64;
+  const int t = tid - 64;  // off-diagonal slot
+  const int nblk = np / NB;
+
+  for (int i = tid; i < np; i += kWideNT) xs[i] = i < n ? (W)b[s.dof_off + i] : (W)0;
+  T buf[CW];
+
+  // ---- forward: L y = b, column layout: (i, j) at C[j*kd + i] ----
+  // chain lane i reads (j0+i, j0+c) at j0*ld + c*kd + i; row i of the
+  // off-diagonal block reads (i, j0+c) at j0*ld + c*kd + (i - j0)
+  if (chainw) {
+    load_cols<T, CW>(buf, Cr, lane, kd, 0);
+  } else if (t < kd && 64 + t < np) {
+    load_cols<T, CW>(buf, Cr, 64 + t, kd, 0);
+  }
+  __syncthreads();
+  for (int bk = 0; bk < nblk; ++bk) {
+    const int j0 = bk * NB;
+    const int64_t jb = (int64_t)j0 * ld;
+    if (chainw) {
+      W xi = xs[j0 + lane];
+      W dd = 0;
+#pragma unroll
+      for (int h = 0; h < NCH; ++h) {
+        if (h > 0) load_cols<T, CW>(buf, Cr, jb + lane, kd, h * CW);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) {
+          const int c = h * CW + cc;
+          dd = (c == lane) ? (W)buf[cc] : dd;
+          buf[cc] = (c < lane && lane - c <= kd) ? buf[cc] : (T)0;
+        }
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) {
+          const int c = h * CW + cc;
+          const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
+          xi = fma(-(W)buf[cc], yc, xi);
+        }
+      }
+      xs[j0 + lane] = xi * dd;
+      if (bk + 1 < nblk) load_cols<T, CW>(buf, Cr, jb + (int64_t)NB * ld + lane, kd, 0);
+    }
+    __syncthreads();
+    if (!chainw) {
+      const int i = j0 + NB + t;
+      if (t < kd && i < np) {
+        const int cmin = i - j0 - kd;  // columns c < cmin lie outside the band
+        W acc = 0;
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) {
+          if (h > 0) load_cols<T, CW>(buf, Cr, jb + (i - j0), kd, h * CW);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int cc = 0; cc < CW; ++cc) {
+            const int c = h * CW + cc;
+            acc = fma(c >= cmin ? (W)buf[cc] : (W)0, xs[j0 + c], acc);
+          }
+        }
+        xs[i] -= acc;
+      }
+      if (bk + 1 < nblk && t < kd && i + NB < np)
+        load_cols<T, CW>(buf, Cr, jb + (int64_t)NB * ld + (i - j0), kd, 0);
+    }
+    __syncthreads();
+  }
+
+  // ---- backward: L^T x = y, row layout: (i, j) at R[i*ld + (i - j)] ----
+  // chain lane i reads (j0+c, j0+i) at j0*ld + c*(ld+1) - i; row i < j0
+  // reads (j0+c, i) at j0*ld + c*(ld+1) + (j0 - i).  Chunks are taken from
+  // the last columns down, the order of the chain.
+  {
+    const int j0 = (nblk - 1) * NB;
+    const int64_t jb = (int64_t)j0 * ld;
+    if (chainw) {
+      load_cols<T, CW>(buf, Rr, jb - lane, ld + 1, NB - CW);
+    } else if (t < kd && j0 - kd + t >= 0) {
+      load_cols<T, CW>(buf, Rr, jb + (kd - t), ld + 1, NB - CW);
+    }
+  }
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int j0 = bk * NB;
+    const int64_t jb = (int64_t)j0 * ld;
+    if (chainw) {
+      W xi = xs[j0 + lane];
+      W dd = 0;
+#pragma unroll
+      for (int h = NCH - 1; h >= 0; --h) {
+        if (h < NCH - 1) load_cols<T, CW>(buf, Rr, jb - lane, ld + 1, h * CW);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int cc = 0; cc < CW; ++cc) {
+          const int c = h * CW + cc;
+          dd = (c == lane) ? (W)buf[cc] : dd;
+          buf[cc] = (c > lane && c - lane <= kd) ? buf[cc] : (T)0;
+        }
+#pragma unroll
+        for (int cc = CW - 1; cc >= 0; --cc) {
+          const int c = h * CW + cc;
+          const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
+          xi = fma(-(W)buf[cc], yc, xi);
+        }
+      }
+      xs[j0 + lane] = xi * dd;
+      if (bk > 0) load_cols<T, CW>(buf, Rr, jb - (int64_t)NB * ld - lane, ld + 1, NB - CW);
+    }
+    __syncthreads();
+    if (!chainw) {
+      const int i = j0 - kd + t;
+      if (t < kd && i >= 0) {
+        // (j0+c, i) lies in the band for c <= kd - (j0 - i) = t
+        W acc = 0;
+#pragma unroll
+        for (int h = NCH - 1; h >= 0; --h) {
+          if (h < NCH - 1) load_cols<T, CW>(buf, Rr, jb + (kd - t), ld + 1, h * CW);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int cc = 0; cc < CW; ++cc) {
+            const int c = h * CW + cc;
+            acc = fma(c <= t ? (W)buf[cc] : (W)0, xs[j0 + c], acc);
+          }
+        }
+        xs[i] -= acc;
+      }
+      if (bk > 0 && t < kd && i - NB >= 0)
+        load_cols<T, CW>(buf, Rr, jb - (int64_t)NB * ld + (kd - t), ld + 1, NB - CW);
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += kWideNT) x[s.dof_off + i] = (double)xs[i];
+}
+
+template <typename T, typename W, int CW>
+void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x) {
+  const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
+  static bool attr_set = false;  // per instantiation
+  if (!attr_set) {
+    hipFuncSetAttribute((const void *)k_band_solve_wide<T, W, CW>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
+    attr_set = true;
+  }
+  k_band_solve_wide<T, W, CW><<<p->n_sub, kWideNT, lds, p->stream>>>(
+      p->subs_d, p->order_d, C, R, p->fac_entries + band_pad_back(p->max_kd), b, x);
+}
+
 template <int NT, int RPT>
 void chol_launch(edd_problem *p) {
   k_band_cholesky<32, NT, 64, RPT><<<p->n_sub, NT, 0, p->stream>>>(
@@ -401,6 +611,13 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x) {
   KTimer kt(p, precision == EDD_F32 ? EDD_KT_BAND_SOLVE32 : EDD_KT_BAND_SOLVE);
   const bool big = p->max_kd > 64;
+  if (p->max_kd > 64 && p->max_kd <= kWideRows) {
+    if (precision == EDD_F32)
+      solve_wide_launch<float, double, 64>(p, p->fac32_d, p->rac32_d, b, x);
+    else
+      solve_wide_launch<double, double, 32>(p, p->fac64_d, p->rac64_d, b, x);
+    return;
+  }
   if (precision == EDD_F32) {
     // FP32 factor entries, FP64 right-hand side and accumulation: the error
     // is a fixed perturbation of K_II rather than arithmetic noise, which

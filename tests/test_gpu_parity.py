@@ -21,7 +21,11 @@ def _cases():
     c3 = w.cantilever3d(13, 9, 7, cuts=(np.array([0, 6, 13]), np.array([0, 4, 9]),
                                         np.array([0, 3, 7])))
     c3.E = 1e-3 + rng.uniform(0, 1, c3.n_el) ** 3
-    return {"2d": c2, "3d": c3, "cfg_small": w.cantilever2d_uniform_64x32()}
+    # interior half-bandwidths 137..257 (> 64): the wide-band substitution
+    c3w = w.cantilever3d(16, 12, 12, cuts=(np.array([0, 7, 16]), np.array([0, 12]),
+                                           np.array([0, 5, 12])))
+    c3w.E = 1e-3 + rng.uniform(0, 1, c3w.n_el) ** 3
+    return {"2d": c2, "3d": c3, "3d_wide": c3w, "cfg_small": w.cantilever2d_uniform_64x32()}
 
 
 CASES = _cases()
@@ -43,7 +47,7 @@ def test_apply_K_parity_and_determinism(name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["2d", "3d"])
+@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide"])
 def test_interior_solve_parity(name):
     require_gpu()
     from paper_1501_06211_amd import edd
@@ -64,7 +68,7 @@ def test_interior_solve_parity(name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["2d", "3d"])
+@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide"])
 def test_schur_apply_parity(name):
     require_gpu()
     wk = CASES[name]
@@ -78,7 +82,7 @@ def test_schur_apply_parity(name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["2d", "3d", "cfg_small"])
+@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide", "cfg_small"])
 @pytest.mark.parametrize("pc", ["identity"])
 def test_solve_parity(name, pc):
     require_gpu()
@@ -135,7 +139,7 @@ def test_error_paths():
 
 
 @pytest.mark.parametrize("mode", ["mixed", "relaxed"])
-@pytest.mark.parametrize("name", ["2d", "3d"])
+@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide"])
 def test_mixed_precision_solve(name, mode):
     """Reduced-precision interior factors (interface refinement, or one
     flexible CG with relaxed operator accuracy): the FP64 true residual
