@@ -208,6 +208,33 @@ def to_sequence_2d(nsteps=60, nx=1024, ny=512, ell=20.0, base_seed=4000,
         yield 1e-3 + _field_to_elements(rho) ** 3
 
 
+def to_sequence_3d(nsteps=60, nx=128, ny=64, nz=64, ell=20.0, base_seed=6000,
+                   blend=0.1):
+    """The density sequence of ``to_sequence_2d`` on a 3D element grid."""
+    phi = gaussian_random_field((nx, ny, nz), ell, base_seed)
+    for k in range(nsteps):
+        if k > 0:
+            g = gaussian_random_field((nx, ny, nz), ell, base_seed + k)
+            phi = (1.0 - blend) * phi + blend * g
+            phi = (phi - phi.mean()) / phi.std()
+        rho = (phi > np.median(phi)).astype(np.float64)
+        yield 1e-3 + _field_to_elements(rho) ** 3
+
+
+def cnn_initial_weights(dim, cin, width, cout, seed, nlayers=4):
+    """Seeded initial weights of the correction network: per layer a tap
+    array of shape (3^dim, c_in, c_out) drawn from N(0, 2 / (3^dim c_in))
+    and zero biases.  Random numbers only; the network itself is not here."""
+    rng = np.random.default_rng(seed)
+    chans = [cin] + [width] * (nlayers - 1) + [cout]
+    out = []
+    for a, b in zip(chans[:-1], chans[1:]):
+        fan_in = 3 ** dim * a
+        W = rng.standard_normal((3 ** dim, a, b)) * np.sqrt(2.0 / fan_in)
+        out.append((W, np.zeros(b)))
+    return out
+
+
 def batch_uneven_problem(p, ell=8.0):
     """Problem ``p`` of the uneven batch: 2D for p < 32, 3D otherwise."""
     seed = 5000 + p
