@@ -77,6 +77,7 @@ extern "C" {
 #define EDD_FLAG_TRUE_RES_RESTART 1 /* recursive residual disagreed; restarted */
 #define EDD_FLAG_MIXED_FALLBACK 2   /* mixed path stalled; fell back to FP64   */
 #define EDD_FLAG_PC_DROPPED 4       /* preconditioner output rejected          */
+#define EDD_FLAG_LEARNED_REJECTED 8 /* network proposal gave no descent; unused */
 
 typedef struct edd_problem edd_problem;
 
@@ -126,6 +127,10 @@ typedef struct edd_solve_opts {
   int interface_weighting; /* 0: M, L of the skeleton as in the paper;        */
                            /* 1: each skeleton element scaled by the mean     */
                            /*    modulus of its two neighbouring elements     */
+  int learned_guess;  /* 1: add the correction network's proposal to the     */
+                      /* initial guess, scaled by the exact minimiser of the */
+                      /* interface energy error along it (needs              */
+                      /* edd_cnn_setup); 0: off                              */
 } edd_solve_opts;
 
 typedef struct edd_solve_stats {
@@ -140,6 +145,8 @@ typedef struct edd_solve_stats {
   double compliance;        /* f^T u (eq. (NumberTen))                        */
   double t_total_ms;        /* wall time of the call                          */
   double t_krylov_ms;       /* interface iteration part                       */
+  double learned_alpha;     /* step taken along the network's proposal (0 if  */
+                            /* off or rejected)                               */
 } edd_solve_stats;
 
 typedef struct edd_info {
@@ -159,7 +166,7 @@ typedef struct edd_info {
  * theta 0.5 in the device-resident form with 4 Lanczos steps of 4 inner
  * iterations (the paper's adaptive form: lanczos_tol 1e-2, inner_tol 1e-3,
  * Section 4), no initial guess, outer_maxit 20, mixed_inner_tol 1e-4,
- * flexible_window 0, interface_weighting 1. */
+ * flexible_window 0, interface_weighting 1, learned_guess 0. */
 void edd_default_opts(edd_solve_opts *o);
 
 /* Build a problem handle from the grid, the subdomain cuts, nu and the
@@ -223,6 +230,42 @@ int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
 int edd_apply_skeleton_op(edd_problem *p, int which, int weighting,
                           const double *x_dev, double *y_dev, double tol,
                           int maxit);
+
+/* ---- correction network (an addition to the paper's method) -----------
+ * A convolution network on the node grid proposes a displacement correction
+ * d ~ K^{-1} r from a stiffness indicator (per node, the mean over adjacent
+ * elements of clip(1 + log10(E_e)/3, 0, 1)) and the residual r divided by
+ * its root mean square over free dofs.  Four layers of 3^dim taps with
+ * dilations 1, 2, 4, 1 and ReLU after the first three; widths 1+dim -> 32
+ * -> 32 -> 32 -> dim.  Activations are node-major FP32, the forward pass
+ * uses FP16 weights with FP32 accumulation, and the master weights are
+ * FP32, trained by Adam (beta 0.9/0.999, eps 1e-8) on the relative squared
+ * L2 loss against e / rms(e).  Parameters are one flat FP32 array: per
+ * layer W[tap][c_in][c_out] (taps in C order over the ([z,] y, x) offsets
+ * -1, 0, 1 times the dilation) followed by b[c_out].
+ * The solver uses the proposal only through edd_solve_opts.learned_guess. */
+
+/* Allocate the network for this problem; width must be 32.  Parameters
+ * start at zero. */
+int edd_cnn_setup(edd_problem *p, int width);
+/* Number of FP32 parameters. */
+int edd_cnn_num_params(edd_problem *p, int64_t *n);
+/* Copy device parameters in (resets the Adam moments) or out. */
+int edd_cnn_set_params(edd_problem *p, const float *params_dev);
+int edd_cnn_get_params(edd_problem *p, float *params_dev);
+/* d = network(E, r) on full-length nodal vectors; d is zero at Dirichlet
+ * dofs.  E_dev: n_el FP64 element moduli for the stiffness indicator, or
+ * NULL for the moduli set last (these need not be the factored ones). */
+int edd_cnn_predict(edd_problem *p, const double *E_dev, const double *r_dev,
+                    double *d_dev);
+/* Loss and its gradient (FP32, parameter layout) for the pair (r, e), where
+ * e is the correction that r calls for; grad_dev may be NULL.  No update. */
+int edd_cnn_loss_grad(edd_problem *p, const double *E_dev, const double *r_dev,
+                      const double *e_dev, float *grad_dev, double *loss);
+/* One Adam step with learning rate lr on the pair (r, e); *loss receives
+ * the loss before the step. */
+int edd_cnn_train_step(edd_problem *p, const double *E_dev, const double *r_dev,
+                       const double *e_dev, double lr, double *loss);
 
 /* Sizes of the problem. */
 int edd_get_info(edd_problem *p, edd_info *info);

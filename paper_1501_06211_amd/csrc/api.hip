@@ -428,6 +428,48 @@ static int solve_relaxed(edd_problem *p, const double *f, double *u,
   return solve_plain(p, f, u, &o2, st, nf);
 }
 
+// Learned initial guess: u += alpha d with d the network's proposal for the
+// residual f - K u and alpha the exact minimiser of the interface energy
+// error along d_G: alpha = <d_G, g - S u_G> / <d_G, S d_G>.  The interior
+// part of u is recomputed by back-substitution, so only u_G matters.
+static int learned_guess(edd_problem *p, const double *f, double *u, const edd_solve_opts *o,
+                         edd_solve_stats *st) {
+  const int D = p->g.dim;
+  const int64_t nG = p->n_gamma * D;
+  if (!o->use_initial_guess) launch_fill(p, p->ndof, 0.0, u);
+  double *r = p->cnn_r_d, *d = p->cnn_dir_d;
+  launch_apply_full(p, u, p->w_full[0]);
+  launch_copy(p, p->ndof, f, r);
+  launch_axpby(p, p->ndof, -1.0, p->w_full[0], 1.0, r);
+  launch_mask_dirichlet(p, r);
+  int rc = cnn_predict(p, nullptr, r, d);
+  if (rc) return rc;
+  double *g = p->w_G[3], *x0 = p->w_G[0], *dG = p->w_G[5], *r0 = p->w_G[6], *t = p->w_G[7];
+  condense(p, f, g, EDD_F64);
+  launch_gather(p, p->gnode_d, p->n_gamma, u, x0);
+  launch_gather(p, p->gnode_d, p->n_gamma, d, dG);
+  apply_S(p, x0, t, EDD_F64);
+  launch_copy(p, nG, g, r0);
+  launch_axpby(p, nG, -1.0, t, 1.0, r0);
+  apply_S(p, dG, t, EDD_F64);
+  {
+    const double *a2[2] = {dG, dG}, *b2[2] = {r0, t};
+    launch_dots(p, nG, 2, a2, b2, S_RES);
+  }
+  rc = read_scalars(p, S_RES, 2);
+  if (rc) return rc;
+  const double num = p->scal_h[S_RES], den = p->scal_h[S_RES + 1];
+  const double alpha = den > 0.0 ? num / den : 0.0;
+  if (!(den > 0.0) || !std::isfinite(alpha)) {
+    st->flags |= EDD_FLAG_LEARNED_REJECTED;
+    st->learned_alpha = 0.0;
+    return EDD_OK;
+  }
+  launch_axpby(p, p->ndof, alpha, d, 1.0, u);
+  st->learned_alpha = alpha;
+  return EDD_OK;
+}
+
 }  // namespace edd
 
 // ---------------------------------------------------------------------------
@@ -452,6 +494,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->mixed_inner_tol = 1e-4;
   o->flexible_window = 0;
   o->interface_weighting = 1;
+  o->learned_guess = 0;
 }
 
 const char *edd_strerror(int code) {
@@ -734,6 +777,57 @@ int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host) {
   return EDD_OK;
 }
 
+int edd_cnn_setup(edd_problem *p, int width) {
+  if (!p) return EDD_EINVAL;
+  int rc = cnn_setup(p, width);
+  if (rc) return rc;
+  if (!p->cnn_r_d) {
+    p->cnn_r_d = (double *)dev_alloc(p, sizeof(double) * p->ndof);
+    p->cnn_dir_d = (double *)dev_alloc(p, sizeof(double) * p->ndof);
+    if (!p->cnn_r_d || !p->cnn_dir_d) return EDD_ENOMEM;
+  }
+  return EDD_OK;
+}
+
+int edd_cnn_num_params(edd_problem *p, int64_t *n) {
+  if (!p || !n) return EDD_EINVAL;
+  if (!p->cnn_nparams) return EDD_ESTATE;
+  *n = p->cnn_nparams;
+  return EDD_OK;
+}
+
+int edd_cnn_set_params(edd_problem *p, const float *params_dev) {
+  if (!p || !params_dev) return EDD_EINVAL;
+  if (!p->cnn_nparams) return EDD_ESTATE;
+  return cnn_set_params(p, params_dev);
+}
+
+int edd_cnn_get_params(edd_problem *p, float *params_dev) {
+  if (!p || !params_dev) return EDD_EINVAL;
+  if (!p->cnn_nparams) return EDD_ESTATE;
+  return cnn_get_params(p, params_dev);
+}
+
+int edd_cnn_predict(edd_problem *p, const double *E_dev, const double *r_dev, double *d_dev) {
+  if (!p || !r_dev || !d_dev) return EDD_EINVAL;
+  if (!p->cnn_nparams || (!E_dev && !p->have_moduli)) return EDD_ESTATE;
+  return cnn_predict(p, E_dev, r_dev, d_dev);
+}
+
+int edd_cnn_loss_grad(edd_problem *p, const double *E_dev, const double *r_dev,
+                      const double *e_dev, float *grad_dev, double *loss) {
+  if (!p || !r_dev || !e_dev || !loss) return EDD_EINVAL;
+  if (!p->cnn_nparams || (!E_dev && !p->have_moduli)) return EDD_ESTATE;
+  return cnn_loss_grad(p, E_dev, r_dev, e_dev, grad_dev, loss);
+}
+
+int edd_cnn_train_step(edd_problem *p, const double *E_dev, const double *r_dev,
+                       const double *e_dev, double lr, double *loss) {
+  if (!p || !r_dev || !e_dev || !loss || !(lr > 0.0)) return EDD_EINVAL;
+  if (!p->cnn_nparams || (!E_dev && !p->have_moduli)) return EDD_ESTATE;
+  return cnn_train_step(p, E_dev, r_dev, e_dev, lr, loss);
+}
+
 int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
                         const edd_solve_opts *o_in, edd_solve_stats *s_out) {
   if (!p || !f_dev || !u_dev) return EDD_EINVAL;
@@ -758,6 +852,12 @@ int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
   if (rc) return rc;
   if (!std::isfinite(nf)) return EDD_EINVAL;
   int status = EDD_OK;
+  if (o.learned_guess && nf > 0.0) {
+    if (!p->cnn_nparams) return EDD_ESTATE;
+    rc = learned_guess(p, f_dev, u_dev, &o, &st);
+    if (rc) return rc;
+    o.use_initial_guess = 1;
+  }
   if (nf == 0.0) {
     launch_fill(p, p->ndof, 0.0, u_dev);
   } else if (o.precision == EDD_MODE_F64) {

@@ -1,8 +1,10 @@
 // Internal declarations of the edd library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -16,6 +18,10 @@ namespace edd {
 //   kDirichlet clamped node
 //   <= -2      interface node, index = -(value) - 2
 constexpr int kDirichlet = -1;
+
+// correction network: layers and hidden width
+constexpr int kCnnLayers = 4;
+constexpr int kCnnWidth = 32;
 __host__ __device__ inline int gamma_code(int g) { return -g - 2; }
 __host__ __device__ inline int gamma_index(int code) { return -code - 2; }
 
@@ -145,6 +151,18 @@ struct edd_problem {
   double *outer_d = nullptr;
   size_t outer_len = 0;
 
+  // correction network (kernels_cnn.hip)
+  int64_t cnn_nparams = 0;
+  int64_t cnn_off[edd::kCnnLayers] = {};
+  int cnn_t = 0;           // Adam steps taken
+  double cnn_nfree = 0.0;  // free dofs (rms normalisation)
+  float *cnn_master_d = nullptr, *cnn_m_d = nullptr, *cnn_v_d = nullptr,
+        *cnn_grad_d = nullptr, *cnn_part_d = nullptr, *cnn_target_d = nullptr;
+  __half *cnn_w16_d = nullptr;
+  float *cnn_act_d[5] = {};  // features, three hidden activations, output
+  float *cnn_g_d[2] = {};    // activation gradients (ping-pong)
+  double *cnn_r_d = nullptr, *cnn_dir_d = nullptr;  // residual and proposal
+
   int last_hip_error = 0;
 
   // kernel timing (edd_set_kernel_timing)
@@ -223,6 +241,17 @@ int precond_apply(edd_problem *p, const double *r, double *z,
 int precond_setup(edd_problem *p);
 int skeleton_op(edd_problem *p, int which, int weighting, const double *x, double *y,
                 double tol, int maxit);
+
+// correction network (kernels_cnn.hip)
+int cnn_setup(edd_problem *p, int width);
+int cnn_set_params(edd_problem *p, const float *params);
+int cnn_get_params(edd_problem *p, float *params);
+// E: element moduli for the stiffness indicator (nullptr: the moduli set last)
+int cnn_predict(edd_problem *p, const double *E, const double *r, double *d);
+int cnn_loss_grad(edd_problem *p, const double *E, const double *r, const double *e,
+                  float *grad, double *loss);
+int cnn_train_step(edd_problem *p, const double *E, const double *r, const double *e,
+                   double lr, double *loss);
 
 // Records HIP events around the launches in its scope when timing is on.
 struct KTimer {

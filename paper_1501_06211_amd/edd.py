@@ -23,6 +23,7 @@ CLAMP_X0, CLAMP_X1, CLAMP_Y0, CLAMP_Y1, CLAMP_Z0, CLAMP_Z1 = 1, 2, 4, 8, 16, 32
 MODE_F64, MODE_MIXED, MODE_RELAXED = 0, 1, 2
 PC_IDENTITY, PC_HTHETA = 0, 1
 FLAG_TRUE_RES_RESTART, FLAG_MIXED_FALLBACK, FLAG_PC_DROPPED = 1, 2, 4
+FLAG_LEARNED_REJECTED = 8
 
 EXPORTS = [
     "edd_default_opts", "edd_setup_mesh", "edd_set_element_moduli",
@@ -30,7 +31,9 @@ EXPORTS = [
     "edd_apply_precond", "edd_get_info", "edd_get_gamma_nodes",
     "edd_get_interior_nodes", "edd_destroy", "edd_strerror",
     "edd_last_hip_error", "edd_set_kernel_timing", "edd_get_kernel_times",
-    "edd_apply_skeleton_op",
+    "edd_apply_skeleton_op", "edd_cnn_setup", "edd_cnn_num_params",
+    "edd_cnn_set_params", "edd_cnn_get_params", "edd_cnn_predict",
+    "edd_cnn_loss_grad", "edd_cnn_train_step",
 ]
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
             "precond", "layouts", "band_solve32"]
@@ -71,6 +74,7 @@ class SolveOpts(ctypes.Structure):
         ("mixed_inner_tol", ctypes.c_double),
         ("flexible_window", ctypes.c_int),
         ("interface_weighting", ctypes.c_int),
+        ("learned_guess", ctypes.c_int),
     ]
 
 
@@ -87,6 +91,7 @@ class SolveStats(ctypes.Structure):
         ("compliance", ctypes.c_double),
         ("t_total_ms", ctypes.c_double),
         ("t_krylov_ms", ctypes.c_double),
+        ("learned_alpha", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -155,6 +160,13 @@ def lib():
     L.edd_set_kernel_timing.argtypes = [vp, i32]
     L.edd_apply_skeleton_op.argtypes = [vp, i32, i32, vp, vp, dbl, i32]
     L.edd_get_kernel_times.argtypes = [vp, ctypes.POINTER(KernelTimes)]
+    L.edd_cnn_setup.argtypes = [vp, i32]
+    L.edd_cnn_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.edd_cnn_set_params.argtypes = [vp, vp]
+    L.edd_cnn_get_params.argtypes = [vp, vp]
+    L.edd_cnn_predict.argtypes = [vp, vp, vp, vp]
+    L.edd_cnn_loss_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
+    L.edd_cnn_train_step.argtypes = [vp, vp, vp, vp, dbl, ctypes.POINTER(dbl)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("edd_default_opts", "edd_strerror"):
@@ -280,6 +292,52 @@ class Problem:
                                        ctypes.byref(st))
         self._check(rc, "edd_solve_interface")
         return u, st.as_dict()
+
+    # ---- correction network -------------------------------------------------
+    def cnn_setup(self, width=32):
+        self._check(lib().edd_cnn_setup(self.h, width), "edd_cnn_setup")
+        n = ctypes.c_int64()
+        self._check(lib().edd_cnn_num_params(self.h, ctypes.byref(n)), "edd_cnn_num_params")
+        return int(n.value)
+
+    def cnn_set_params(self, params: torch.Tensor):
+        self._check(lib().edd_cnn_set_params(self.h, _ptr(params, torch.float32)),
+                    "edd_cnn_set_params")
+
+    def cnn_get_params(self):
+        n = ctypes.c_int64()
+        self._check(lib().edd_cnn_num_params(self.h, ctypes.byref(n)), "edd_cnn_num_params")
+        out = torch.empty(int(n.value), dtype=torch.float32, device=self.device)
+        self._check(lib().edd_cnn_get_params(self.h, _ptr(out, torch.float32)),
+                    "edd_cnn_get_params")
+        return out
+
+    @staticmethod
+    def _optr(E):
+        return None if E is None else _ptr(E)
+
+    def cnn_predict(self, r, out=None, E=None):
+        if out is None:
+            out = torch.empty_like(r)
+        self._check(lib().edd_cnn_predict(self.h, self._optr(E), _ptr(r), _ptr(out)),
+                    "edd_cnn_predict")
+        return out
+
+    def cnn_loss_grad(self, r, e, E=None):
+        n = ctypes.c_int64()
+        self._check(lib().edd_cnn_num_params(self.h, ctypes.byref(n)), "edd_cnn_num_params")
+        g = torch.empty(int(n.value), dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._check(lib().edd_cnn_loss_grad(self.h, self._optr(E), _ptr(r), _ptr(e),
+                                            _ptr(g, torch.float32), ctypes.byref(loss)),
+                    "edd_cnn_loss_grad")
+        return float(loss.value), g
+
+    def cnn_train_step(self, r, e, lr=1e-3, E=None):
+        loss = ctypes.c_double()
+        self._check(lib().edd_cnn_train_step(self.h, self._optr(E), _ptr(r), _ptr(e), lr,
+                                             ctypes.byref(loss)), "edd_cnn_train_step")
+        return float(loss.value)
 
     def solve_interior(self, b, out=None, precision=F64):
         if out is None:
