@@ -231,6 +231,32 @@ int edd_apply_skeleton_op(edd_problem *p, int which, int weighting,
                           const double *x_dev, double *y_dev, double tol,
                           int maxit);
 
+/* ---- many problems and tile shapes ------------------------------------ */
+
+/* Solve n independent problems concurrently: a pool of nthreads host
+ * threads (<= 0: 16) drives the handles, each on its own stream, so the
+ * GPU overlaps their kernels.  The handles must be distinct and should be
+ * created on distinct streams (one stream serialises them).  stats (n
+ * entries) may be NULL; each entry's t_total_ms is that problem's latency.
+ * Returns the first error, else EDD_NOT_CONVERGED if any problem missed
+ * the tolerance, else EDD_OK. */
+int edd_solve_batch(edd_problem *const *ps, int n, const double *const *f_dev,
+                    double *const *u_dev, const edd_solve_opts *o,
+                    edd_solve_stats *stats, int nthreads);
+
+/* Autotuner for the batched interior substitution: times every substitution
+ * variant valid for this problem's bands (1-3: one row per thread with an
+ * owner wavefront per diagonal block, 64/256/512 threads per subdomain;
+ * 4-5: wide bands, a dedicated chain wavefront and 1024 threads, two load
+ * chunk widths) on the current factors, for FP64 and (if present) FP32
+ * factors, and keeps the fastest.  Results are cached per shape class
+ * (device, dimension, subdomain count, band extents) for the process;
+ * force != 0 re-times.  variants (2 ints, FP64 then FP32) may be NULL.
+ * Needs edd_set_element_moduli.  Synchronises. */
+int edd_autotune(edd_problem *p, int force, int *variants);
+/* Choose the substitution variants by hand (0 = default by bandwidth). */
+int edd_set_solve_variants(edd_problem *p, const int *variants);
+
 /* ---- correction network (an addition to the paper's method) -----------
  * A convolution network on the node grid proposes a displacement correction
  * d ~ K^{-1} r from a stiffness indicator (per node, the mean over adjacent

@@ -13,7 +13,13 @@
 //
 // Mixed mode: iterative refinement on the interface problem, the inner
 // interface solves using FP32 interior factors (see solve_mixed).
+#include <array>
+#include <atomic>
 #include <chrono>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <cmath>
 #include <cstring>
 
@@ -24,6 +30,9 @@ using namespace edd;
 namespace edd {
 
 // scalar slots in p->scal_d
+// internal status: the reduced-precision phase of a relaxed solve stalled
+constexpr int EDD_ESTALL = 100;
+
 enum : int {
   S_RR = 0,
   S_FF = 1,
@@ -215,11 +224,24 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   if (rc) return rc;
   int status = EDD_OK;
   int k = 0;
+  int k_switch = -1;
+  double rr_switch = 0.0;
   while (std::sqrt(rr) > tol_abs) {
     if (k >= maxit) { status = EDD_NOT_CONVERGED; break; }
     // relaxed operator accuracy: once the residual is small, the S applies
     // may carry a larger error without spoiling the attainable accuracy
-    if (relax_abs > 0.0 && std::sqrt(rr) <= relax_abs) prec = EDD_F32;
+    if (relax_abs > 0.0 && prec != EDD_F32 && std::sqrt(rr) <= relax_abs) {
+      prec = EDD_F32;
+      k_switch = k;
+      rr_switch = rr;
+    }
+    // after the switch the residual must keep falling (at least 10x per 50
+    // iterations); otherwise the reduced-precision phase has stalled
+    if (k_switch >= 0 && k - k_switch >= 50) {
+      if (rr > 1e-2 * rr_switch) { status = EDD_ESTALL; break; }
+      k_switch = k;
+      rr_switch = rr;
+    }
     const double *zp = r;
     if (!pc_identity) {
       rc = precond_apply(p, r, z, o, st, prec == EDD_F32);
@@ -412,7 +434,12 @@ static int solve_relaxed(edd_problem *p, const double *f, double *u,
   int status = interface_fcg(p, g, x, EDD_F64, tol_abs, guess, o, st, o->maxit, window,
                              &its, o->mixed_inner_tol * r0);
   st->iterations += its;
-  if (status == EDD_EBREAKDOWN || status < 0) return status;
+  if (status == EDD_ESTALL) {
+    st->flags |= EDD_FLAG_MIXED_FALLBACK;
+    status = EDD_NOT_CONVERGED;
+  } else if (status == EDD_EBREAKDOWN || status < 0) {
+    return status;
+  }
   back_substitute(p, f, x, u, EDD_F64);
   double rel = 0.0;
   rc = true_residual(p, f, u, &rel);
@@ -420,9 +447,10 @@ static int solve_relaxed(edd_problem *p, const double *f, double *u,
   st->rel_residual = rel;
   st->outer_iterations = 1;
   if (rel <= o->tol) return EDD_OK;
-  if (status == EDD_NOT_CONVERGED) return status;
-  // the recursive residual drifted under the relaxed applies: FP64 restart
-  st->flags |= EDD_FLAG_TRUE_RES_RESTART;
+  if (status == EDD_NOT_CONVERGED && !(st->flags & EDD_FLAG_MIXED_FALLBACK)) return status;
+  // the reduced-precision phase stalled, or the recursive residual drifted
+  // under the relaxed applies: FP64 restart from the current iterate
+  if (!(st->flags & EDD_FLAG_MIXED_FALLBACK)) st->flags |= EDD_FLAG_TRUE_RES_RESTART;
   edd_solve_opts o2 = *o;
   o2.use_initial_guess = 1;
   return solve_plain(p, f, u, &o2, st, nf);
@@ -775,6 +803,120 @@ int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host) {
   if (!p || !nodes_host) return EDD_EINVAL;
   std::memcpy(nodes_host, p->inode.data(), sizeof(int32_t) * p->n_inodes);
   return EDD_OK;
+}
+
+int edd_autotune(edd_problem *p, int force, int *variants) {
+  if (!p) return EDD_EINVAL;
+  if (!p->have_moduli) return EDD_ESTATE;
+  static std::mutex mu;
+  static std::map<std::string, std::array<int, 2>> cache;
+  hipDeviceProp_t prop;
+  int rc = check_hip(p, hipGetDeviceProperties(&prop, p->device));
+  if (rc) return rc;
+  // shape class: device, dimension, subdomain count and band extents
+  const std::string key = std::string(prop.gcnArchName) + "|" + std::to_string(p->g.dim) + "|" +
+                          std::to_string(p->n_sub) + "|" + std::to_string(p->max_kd) + "|" +
+                          std::to_string(p->max_np) + "|" + std::to_string(p->fac_entries);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (!force && it != cache.end()) {
+      p->solve_variant[0] = it->second[0];
+      p->solve_variant[1] = it->second[1];
+      if (variants) { variants[0] = it->second[0]; variants[1] = it->second[1]; }
+      return EDD_OK;
+    }
+  }
+  hipEvent_t e0, e1;
+  rc = check_hip(p, hipEventCreate(&e0));
+  if (rc) return rc;
+  rc = check_hip(p, hipEventCreate(&e1));
+  if (rc) return rc;
+  double *b = p->w_I[0], *x = p->w_I[1];
+  launch_fill(p, p->n_idofs, 1.0, b);
+  const bool kt = p->kt_enabled;
+  p->kt_enabled = false;
+  for (int f = 0; f < 2 && rc == 0; ++f) {
+    const int prec = f ? EDD_F32 : EDD_F64;
+    if (f && !p->fac32_d) break;
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int v = 1; v <= kBandSolveVariants && rc == 0; ++v) {
+      if (!band_solve_variant_ok(p, v)) continue;
+      p->solve_variant[f] = v;
+      launch_band_solve(p, prec, b, x);  // warm-up (first-launch costs)
+      hipEventRecord(e0, p->stream);
+      for (int r = 0; r < 3; ++r) launch_band_solve(p, prec, b, x);
+      hipEventRecord(e1, p->stream);
+      rc = check_hip(p, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      if (!rc) rc = check_hip(p, hipEventElapsedTime(&ms, e0, e1));
+      if (!rc && (best == 0 || ms < best_ms)) {
+        best = v;
+        best_ms = ms;
+      }
+    }
+    p->solve_variant[f] = best;
+  }
+  p->kt_enabled = kt;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = {p->solve_variant[0], p->solve_variant[1]};
+  }
+  if (variants) { variants[0] = p->solve_variant[0]; variants[1] = p->solve_variant[1]; }
+  return EDD_OK;
+}
+
+int edd_set_solve_variants(edd_problem *p, const int *variants) {
+  if (!p || !variants) return EDD_EINVAL;
+  for (int f = 0; f < 2; ++f)
+    if (!band_solve_variant_ok(p, variants[f])) return EDD_EINVAL;
+  p->solve_variant[0] = variants[0];
+  p->solve_variant[1] = variants[1];
+  return EDD_OK;
+}
+
+int edd_solve_batch(edd_problem *const *ps, int n, const double *const *f_dev,
+                    double *const *u_dev, const edd_solve_opts *o,
+                    edd_solve_stats *stats, int nthreads) {
+  if (n < 0 || (n > 0 && (!ps || !f_dev || !u_dev))) return EDD_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ps[i] || !f_dev[i] || !u_dev[i]) return EDD_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ps[j] == ps[i]) return EDD_EINVAL;  // one solve per handle at a time
+  }
+  if (n == 0) return EDD_OK;
+  int nt = nthreads > 0 ? nthreads : 16;
+  if (nt > n) nt = n;
+  std::vector<int> rcs(n, EDD_OK);
+  std::vector<edd_solve_stats> st(n);
+  std::atomic<int> next{0};
+  auto work = [&] {
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) break;
+      if (hipSetDevice(ps[i]->device) != hipSuccess) {
+        rcs[i] = EDD_EHIP;
+        continue;
+      }
+      rcs[i] = edd_solve_interface(ps[i], f_dev[i], u_dev[i], o, &st[i]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto &t : pool) t.join();
+  if (stats)
+    for (int i = 0; i < n; ++i) stats[i] = st[i];
+  int worst = EDD_OK;
+  for (int i = 0; i < n; ++i) {
+    if (rcs[i] < 0) return rcs[i];
+    if (rcs[i] == EDD_NOT_CONVERGED) worst = EDD_NOT_CONVERGED;
+  }
+  return worst;
 }
 
 int edd_cnn_setup(edd_problem *p, int width) {

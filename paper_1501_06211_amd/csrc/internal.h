@@ -100,6 +100,7 @@ struct edd_problem {
   double *rac64_d = nullptr;  // row-major copies used by the backward sweep
   float *rac32_d = nullptr;
   bool have_moduli = false;
+  int solve_variant[2] = {0, 0};  // substitution variant, FP64 / FP32 factors
 
   // skeleton operators of the interface preconditioner
   int sk_state = -1;            // weighting the device operators hold (-1 none)
@@ -197,6 +198,8 @@ void launch_band_cholesky(edd_problem *p);
 void launch_band_layouts(edd_problem *p);
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x);
+bool band_solve_variant_ok(const edd_problem *p, int v);
+constexpr int kBandSolveVariants = 5;
 
 // kernels_vec.hip
 // dots: out[k] = sum_i a_k[i] * b_k[i] for k < nd (nd <= 4), written to

@@ -18,6 +18,8 @@
 // (kBandPadFront / band_pad_back entries), so panel loads are issued
 // unconditionally and out-of-band values are discarded with a select; only
 // stores are predicated.  This keeps many loads in flight per thread.
+#include <mutex>
+
 #include "internal.h"
 
 namespace edd {
@@ -544,12 +546,11 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
 template <typename T, typename W, int CW>
 void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x) {
   const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
-  static bool attr_set = false;  // per instantiation
-  if (!attr_set) {
+  static std::once_flag attr_once;  // per instantiation (LDS limit is per device)
+  std::call_once(attr_once, [&] {
     hipFuncSetAttribute((const void *)k_band_solve_wide<T, W, CW>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
-    attr_set = true;
-  }
+  });
   k_band_solve_wide<T, W, CW><<<p->n_sub, kWideNT, lds, p->stream>>>(
       p->subs_d, p->order_d, C, R, p->fac_entries + band_pad_back(p->max_kd), b, x);
 }
@@ -563,12 +564,11 @@ void chol_launch(edd_problem *p) {
 template <typename T, typename W, int NT>
 void solve_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x) {
   const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
-  static bool attr_set = false;  // per instantiation
-  if (!attr_set) {
+  static std::once_flag attr_once;  // per instantiation (LDS limit is per device)
+  std::call_once(attr_once, [&] {
     hipFuncSetAttribute((const void *)k_band_solve<T, W, NT>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
-    attr_set = true;
-  }
+  });
   k_band_solve<T, W, NT><<<p->n_sub, NT, lds, p->stream>>>(p->subs_d, p->order_d,
                                                           C, R, b, x);
 }
@@ -607,27 +607,46 @@ void launch_band_layouts(edd_problem *p) {
                                                        p->fac64_d, p->rac64_d);
 }
 
+// Substitution variants (the tile shapes the autotuner chooses between):
+//   1, 2, 3  one row per thread, owner wavefront per diagonal block,
+//            64 / 256 / 512 threads per subdomain
+//   4, 5     wide bands (kd <= kWideRows): dedicated chain wavefront, 1024
+//            threads, 16 / 32 (FP64) or 32 / 64 (FP32) columns per load chunk
+//   0        the default choice from the half bandwidth
+bool band_solve_variant_ok(const edd_problem *p, int v) {
+  if (v >= 1 && v <= 3) return true;
+  if (v == 4 || v == 5) return p->max_kd <= kWideRows;
+  return v == 0;
+}
+
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x) {
   KTimer kt(p, precision == EDD_F32 ? EDD_KT_BAND_SOLVE32 : EDD_KT_BAND_SOLVE);
-  const bool big = p->max_kd > 64;
-  if (p->max_kd > 64 && p->max_kd <= kWideRows) {
-    if (precision == EDD_F32)
-      solve_wide_launch<float, double, 64>(p, p->fac32_d, p->rac32_d, b, x);
-    else
-      solve_wide_launch<double, double, 32>(p, p->fac64_d, p->rac64_d, b, x);
-    return;
-  }
-  if (precision == EDD_F32) {
-    // FP32 factor entries, FP64 right-hand side and accumulation: the error
-    // is a fixed perturbation of K_II rather than arithmetic noise, which
-    // the Schur complement of smooth interface vectors (a small difference
-    // of large terms) would amplify
-    if (big) solve_launch<float, double, 512>(p, p->fac32_d, p->rac32_d, b, x);
-    else solve_launch<float, double, 64>(p, p->fac32_d, p->rac32_d, b, x);
+  const bool f32 = precision == EDD_F32;
+  int v = p->solve_variant[f32 ? 1 : 0];
+  if (v == 0) v = p->max_kd <= 64 ? 1 : (p->max_kd <= kWideRows ? 5 : 3);
+  // FP32 factor entries use FP64 right-hand sides and accumulation: the error
+  // is then a fixed perturbation of K_II rather than arithmetic noise, which
+  // the Schur complement of smooth interface vectors (a small difference of
+  // large terms) would amplify
+  if (f32) {
+    const float *C = p->fac32_d, *R = p->rac32_d;
+    switch (v) {
+      case 1: solve_launch<float, double, 64>(p, C, R, b, x); break;
+      case 2: solve_launch<float, double, 256>(p, C, R, b, x); break;
+      case 3: solve_launch<float, double, 512>(p, C, R, b, x); break;
+      case 4: solve_wide_launch<float, double, 32>(p, C, R, b, x); break;
+      default: solve_wide_launch<float, double, 64>(p, C, R, b, x); break;
+    }
   } else {
-    if (big) solve_launch<double, double, 512>(p, p->fac64_d, p->rac64_d, b, x);
-    else solve_launch<double, double, 64>(p, p->fac64_d, p->rac64_d, b, x);
+    const double *C = p->fac64_d, *R = p->rac64_d;
+    switch (v) {
+      case 1: solve_launch<double, double, 64>(p, C, R, b, x); break;
+      case 2: solve_launch<double, double, 256>(p, C, R, b, x); break;
+      case 3: solve_launch<double, double, 512>(p, C, R, b, x); break;
+      case 4: solve_wide_launch<double, double, 16>(p, C, R, b, x); break;
+      default: solve_wide_launch<double, double, 32>(p, C, R, b, x); break;
+    }
   }
 }
 

@@ -33,7 +33,8 @@ EXPORTS = [
     "edd_last_hip_error", "edd_set_kernel_timing", "edd_get_kernel_times",
     "edd_apply_skeleton_op", "edd_cnn_setup", "edd_cnn_num_params",
     "edd_cnn_set_params", "edd_cnn_get_params", "edd_cnn_predict",
-    "edd_cnn_loss_grad", "edd_cnn_train_step",
+    "edd_cnn_loss_grad", "edd_cnn_train_step", "edd_solve_batch", "edd_autotune",
+    "edd_set_solve_variants",
 ]
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
             "precond", "layouts", "band_solve32"]
@@ -160,6 +161,11 @@ def lib():
     L.edd_set_kernel_timing.argtypes = [vp, i32]
     L.edd_apply_skeleton_op.argtypes = [vp, i32, i32, vp, vp, dbl, i32]
     L.edd_get_kernel_times.argtypes = [vp, ctypes.POINTER(KernelTimes)]
+    L.edd_solve_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
+                                  ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
+                                  ctypes.POINTER(SolveStats), i32]
+    L.edd_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.edd_set_solve_variants.argtypes = [vp, ctypes.POINTER(i32)]
     L.edd_cnn_setup.argtypes = [vp, i32]
     L.edd_cnn_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.edd_cnn_set_params.argtypes = [vp, vp]
@@ -293,6 +299,16 @@ class Problem:
         self._check(rc, "edd_solve_interface")
         return u, st.as_dict()
 
+    # ---- tile shapes -----------------------------------------------------------
+    def autotune(self, force=False):
+        v = (ctypes.c_int * 2)()
+        self._check(lib().edd_autotune(self.h, int(force), v), "edd_autotune")
+        return int(v[0]), int(v[1])
+
+    def set_solve_variants(self, f64, f32):
+        v = (ctypes.c_int * 2)(int(f64), int(f32))
+        self._check(lib().edd_set_solve_variants(self.h, v), "edd_set_solve_variants")
+
     # ---- correction network -------------------------------------------------
     def cnn_setup(self, width=32):
         self._check(lib().edd_cnn_setup(self.h, width), "edd_cnn_setup")
@@ -403,3 +419,18 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch(problems, fs, us, nthreads=0, **opts):
+    """Solve independent problems concurrently (edd_solve_batch).  Returns
+    (status, [stats dict per problem])."""
+    n = len(problems)
+    hs = (ctypes.c_void_p * n)(*[p.h.value for p in problems])
+    fp = (ctypes.c_void_p * n)(*[_ptr(f).value for f in fs])
+    up = (ctypes.c_void_p * n)(*[_ptr(u).value for u in us])
+    o = default_opts(**opts)
+    st = (SolveStats * n)()
+    rc = lib().edd_solve_batch(hs, n, fp, up, ctypes.byref(o), st, int(nthreads))
+    if rc not in (OK, NOT_CONVERGED):
+        raise EddError(rc, "edd_solve_batch")
+    return rc, [s.as_dict() for s in st]

@@ -1,0 +1,103 @@
+"""Substitution variants chosen by the autotuner, and many independent
+problems solved concurrently through edd_solve_batch, against the oracle and
+against one-at-a-time solves."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import workloads as w
+from oracle import dd, fe
+
+from gpu_util import interior_perm, make_problem, require_gpu, to_cuda, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _wide():
+    rng = np.random.default_rng(11)
+    p = w.cantilever3d(16, 12, 12, cuts=(np.array([0, 7, 16]), np.array([0, 12]),
+                                         np.array([0, 5, 12])))
+    p.E = 1e-3 + rng.uniform(0, 1, p.n_el) ** 3
+    return p
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+def test_every_substitution_variant_matches_the_oracle(variant):
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _wide()
+    prob = make_problem(p)
+    prob.set_solve_variants(variant, variant)
+    perm = interior_perm(p, prob)
+    KII, *_ = dd.blocks(p)
+    b = np.random.default_rng(2).standard_normal(prob.n_interior_dofs)
+    xr = spla.spsolve(KII.tocsc(), b[perm])
+    x = to_np(prob.solve_interior(to_cuda(b)))
+    x32 = to_np(prob.solve_interior(to_cuda(b), precision=edd.F32))
+    e64 = np.linalg.norm(x[perm] - xr) / np.linalg.norm(xr)
+    e32 = np.linalg.norm(x32[perm] - xr) / np.linalg.norm(xr)
+    print(f"variant {variant}: FP64 {e64:.2e}, FP32 factors {e32:.2e}")
+    assert e64 <= 1e-12 and e32 <= 1e-5
+    prob.close()
+
+
+def test_autotune_picks_valid_variants_and_caches():
+    require_gpu()
+    p = _wide()
+    prob = make_problem(p)
+    v = prob.autotune(force=True)
+    assert all(1 <= x <= 5 for x in v)
+    prob2 = make_problem(p)
+    assert prob2.autotune() == v  # same shape class: cached
+    u, st = prob2.solve(to_cuda(p.f), tol=1e-12, maxit=3000)
+    uref = fe.solve_direct(p)
+    assert np.linalg.norm(to_np(u) - uref) <= 1e-8 * np.linalg.norm(uref)
+    prob.close()
+    prob2.close()
+
+
+def _batch_problems():
+    # small members of the uneven batch: 2D and 3D, each with its own field
+    probs = []
+    for k, (nx, ny) in enumerate([(64, 32), (80, 40), (96, 48)]):
+        p = w.cantilever2d(nx, ny, E=w.simp_moduli(np.random.default_rng(k).uniform(0, 1, nx * ny)))
+        probs.append(p)
+    for k, (nx, ny, nz) in enumerate([(16, 16, 16), (24, 16, 16), (32, 20, 20)]):
+        E = w.simp_moduli(np.random.default_rng(10 + k).uniform(0, 1, nx * ny * nz))
+        probs.append(w.cantilever3d(nx, ny, nz, cuts=(w.even_cuts(nx, 16), w.even_cuts(ny, 16),
+                                                      w.even_cuts(nz, 16)), E=E))
+    return probs
+
+
+def test_batch_matches_single_solves_and_the_oracle():
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    ws = _batch_problems()
+    streams = [torch.cuda.Stream() for _ in ws]
+    probs = []
+    for wk, s in zip(ws, streams):
+        prob = edd.Problem.from_workload(wk, stream=s)
+        prob.set_element_moduli(torch.tensor(wk.E, device="cuda"))
+        prob.autotune()
+        probs.append(prob)
+    fs = [to_cuda(wk.f) for wk in ws]
+    us = [torch.zeros_like(f) for f in fs]
+    torch.cuda.synchronize()
+    rc, stats = edd.solve_batch(probs, fs, us, tol=1e-10, maxit=4000)
+    torch.cuda.synchronize()
+    assert rc == edd.OK
+    for wk, prob, f, u, st in zip(ws, probs, fs, us, stats):
+        u1, st1 = prob.solve(f, tol=1e-10, maxit=4000)
+        torch.cuda.synchronize()
+        assert torch.equal(u, u1), wk.name  # deterministic kernels, same launches
+        assert st["iterations"] == st1["iterations"]
+        assert st["rel_residual"] <= 1e-10
+    # one member against the oracle's direct solve
+    uref = fe.solve_direct(ws[3])
+    assert np.linalg.norm(to_np(us[3]) - uref) <= 1e-7 * np.linalg.norm(uref)
+    lat = [s["t_total_ms"] for s in stats]
+    print(f"batch of {len(ws)}: iterations {[s['iterations'] for s in stats]}, "
+          f"latency ms {np.round(lat, 1).tolist()}")
+    for prob in probs:
+        prob.close()
