@@ -99,6 +99,13 @@ typedef struct edd_mesh_desc {
   int clamp_faces;      /* EDD_CLAMP_* bitmask; at least one face            */
   int factor_precision; /* EDD_F64 and/or EDD_F32: which interior factors    */
                         /* edd_set_element_moduli builds                     */
+  int dissect;          /* 3D interior solves: split a subdomain's interior  */
+                        /* into two band blocks and a separator plane (one  */
+                        /* level of nested dissection) so that more         */
+                        /* workgroups share its substitution; -1: when its  */
+                        /* band work exceeds 1.5x the median or the problem */
+                        /* has few subdomains, 0: never, 1: every subdomain */
+                        /* with at least 5 planes; 2D problems never split  */
 } edd_mesh_desc;
 
 typedef struct edd_solve_opts {

@@ -560,6 +560,7 @@ static int validate_desc(const edd_mesh_desc *d) {
   if (!(d->nu > -1.0 && d->nu < 0.5)) return EDD_EINVAL;
   if ((d->clamp_faces & ((1 << (2 * d->dim)) - 1)) == 0) return EDD_EINVAL;
   if (!(d->factor_precision & (EDD_F64 | EDD_F32))) return EDD_EINVAL;
+  if (d->dissect < -1 || d->dissect > 1) return EDD_EINVAL;
   int64_t nodes = 1;
   for (int a = 0; a < d->dim; ++a) {
     if (d->nel[a] < 1 || d->nel[a] > (1 << 20)) return EDD_EINVAL;
@@ -594,6 +595,7 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
     p->alloc_ctx = a->ctx;
   }
   p->factor_precision = d->factor_precision;
+  p->dissect = d->dissect;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return EDD_EHIP; }
   rc = build_geometry(p, d);
   if (rc) { delete p; return rc; }
@@ -610,9 +612,16 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
   EDD_TRY_ALLOC(p->nmap_d, int, p->n_nodes);
   EDD_TRY_ALLOC(p->inode_d, int, std::max<int64_t>(1, p->n_inodes));
   EDD_TRY_ALLOC(p->gnode_d, int, std::max<int64_t>(1, p->n_gamma));
-  EDD_TRY_ALLOC(p->subs_d, SubDesc, p->n_sub);
-  EDD_TRY_ALLOC(p->order_d, int, p->n_sub);
-  EDD_TRY_ALLOC(p->info_d, int, p->n_sub);
+  EDD_TRY_ALLOC(p->subs_d, SubDesc, p->n_blk);
+  EDD_TRY_ALLOC(p->order_d, int, p->n_blk);
+  EDD_TRY_ALLOC(p->order_leaf_d, int, p->n_blk);
+  EDD_TRY_ALLOC(p->order_sep_d, int, std::max(1, p->n_sep));
+  EDD_TRY_ALLOC(p->info_d, int, p->n_blk);
+  if (p->n_sep > 0) {
+    EDD_TRY_ALLOC(p->seps_d, SepDesc, p->n_sep);
+    EDD_TRY_ALLOC(p->W64_d, double, p->w_entries);
+    if (p->factor_precision & EDD_F32) EDD_TRY_ALLOC(p->W32_d, float, p->w_entries);
+  }
   EDD_TRY_ALLOC(p->E_d, double, p->n_el);
   {
     // band storage with padding on both sides (unconditional panel loads)
@@ -653,8 +662,11 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
   up(p->nmap_d, p->nmap_host.data(), sizeof(int) * p->n_nodes);
   up(p->inode_d, p->inode.data(), sizeof(int) * p->n_inodes);
   up(p->gnode_d, p->gnode.data(), sizeof(int) * p->n_gamma);
-  up(p->subs_d, p->subs.data(), sizeof(SubDesc) * p->n_sub);
-  up(p->order_d, p->order.data(), sizeof(int) * p->n_sub);
+  up(p->subs_d, p->subs.data(), sizeof(SubDesc) * p->n_blk);
+  up(p->order_d, p->order.data(), sizeof(int) * p->n_blk);
+  up(p->order_leaf_d, p->order_leaf.data(), sizeof(int) * p->order_leaf.size());
+  up(p->order_sep_d, p->order_sep.data(), sizeof(int) * p->order_sep.size());
+  if (p->n_sep > 0) up(p->seps_d, p->seps.data(), sizeof(SepDesc) * p->n_sep);
   up(p->scal_d, p->scal_h, sizeof(double) * S_TOTAL);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) { edd_destroy(p); return EDD_EHIP; }
@@ -685,10 +697,10 @@ int edd_set_element_moduli(edd_problem *p, const void *E_dev, int dtype) {
   if (p->scal_h[S_BAD] != 0.0) return EDD_EINVAL;
   launch_assemble_band(p);
   launch_band_cholesky(p);
-  std::vector<int> info(p->n_sub, 0);
+  std::vector<int> info(p->n_blk, 0);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess)
-    e = hipMemcpyAsync(info.data(), p->info_d, sizeof(int) * p->n_sub,
+    e = hipMemcpyAsync(info.data(), p->info_d, sizeof(int) * p->n_blk,
                        hipMemcpyDeviceToHost, p->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return check_hip(p, e);
@@ -815,7 +827,7 @@ int edd_autotune(edd_problem *p, int force, int *variants) {
   if (rc) return rc;
   // shape class: device, dimension, subdomain count and band extents
   const std::string key = std::string(prop.gcnArchName) + "|" + std::to_string(p->g.dim) + "|" +
-                          std::to_string(p->n_sub) + "|" + std::to_string(p->max_kd) + "|" +
+                          std::to_string(p->n_blk) + "|" + std::to_string(p->max_kd) + "|" +
                           std::to_string(p->max_np) + "|" + std::to_string(p->fac_entries);
   {
     std::lock_guard<std::mutex> lk(mu);

@@ -38,6 +38,11 @@ struct Geom {
 // coordinates along the axes ax[0] (fastest), ax[1], ax[2] (slowest);
 // local dof p = dim*l + comp.  The lower Cholesky factor is stored by
 // columns: entry (q, p), 0 <= q-p <= kd, at fac[fac_off + p*(kd+1) + q-p].
+//
+// A band block is a whole subdomain interior (kind 0) or, when the interior
+// is dissected, one of its two halves (kind 1, ordered so that the plane next
+// to the separator comes last: dir = -1 runs the slow axis downwards from
+// lo) or the separator plane itself (kind 2, stored with full bandwidth).
 struct SubDesc {
   int n;       // interior dofs
   int kd;      // half bandwidth
@@ -46,8 +51,21 @@ struct SubDesc {
   int len[3];  // box length along local axes (fast, mid, slow)
   int ax[3];   // global axis of each local axis
   int lo[3];   // box origin, indexed by global axis
+  int dir;     // +1, or -1: the slow local axis runs from lo downwards
+  int kind;    // 0 whole interior, 1 half, 2 separator
+  int sep;     // separator record of a dissected interior, else -1
   int64_t dof_off;  // offset in interior vectors
   int64_t fac_off;  // offset in band storage (entries)
+};
+
+// A dissected interior: halves a, b and separator s (band block ids).  The
+// last ns rows of each half couple to the ns separator dofs through
+// W_h = L_h,tail^{-1} K(tail_h, S), stored row-major (tail row, separator
+// column) at w_off (half a) and w_off + ns*ns (half b).
+struct SepDesc {
+  int a, b, s;
+  int ns;
+  int64_t w_off;
 };
 
 }  // namespace edd
@@ -67,8 +85,14 @@ struct edd_problem {
   int factor_precision = EDD_F64;
 
   // host bookkeeping
-  std::vector<edd::SubDesc> subs;
-  std::vector<int> order;  // launch order of subdomains (largest first)
+  int dissect = -1;
+  int n_blk = 0;           // band blocks (subdomains, halves and separators)
+  std::vector<edd::SubDesc> subs;   // band blocks
+  std::vector<int> order;  // launch order of band blocks (largest first)
+  std::vector<int> order_leaf, order_sep;  // halves and whole interiors / separators
+  std::vector<edd::SepDesc> seps;
+  int n_sep = 0;
+  int64_t w_entries = 0;
   std::vector<int> inode, gnode, nmap_host;
   int64_t fac_entries = 0;
   int max_kd = 0, max_n = 0, max_np = 0;
@@ -92,6 +116,10 @@ struct edd_problem {
   int *nmap_d = nullptr, *inode_d = nullptr, *gnode_d = nullptr;
   edd::SubDesc *subs_d = nullptr;
   int *order_d = nullptr;
+  int *order_leaf_d = nullptr, *order_sep_d = nullptr;
+  edd::SepDesc *seps_d = nullptr;
+  double *W64_d = nullptr;  // separator couplings (see SepDesc)
+  float *W32_d = nullptr;
   int *info_d = nullptr;     // per-subdomain factorisation status
   double *E_d = nullptr;     // element moduli (FP64 copy)
   double *fac64_d = nullptr;  // band storage (padded allocation)

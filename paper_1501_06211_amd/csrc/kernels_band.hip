@@ -398,10 +398,12 @@ __device__ inline __amdgpu_buffer_rsrc_t band_rsrc(const T *base, int64_t entrie
                                            0x00020000);
 }
 
+// phase 0: both sweeps; 1: forward sweep only (y = L^{-1} b written to x);
+// 2: backward sweep only (x = L^{-T} b).
 template <typename T, typename W, int CW>
 __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
     const SubDesc *__restrict__ subs, const int *__restrict__ order,
-    const T *__restrict__ Cs, const T *__restrict__ Rs, int64_t fac_len,
+    const T *__restrict__ Cs, const T *__restrict__ Rs, int64_t fac_len, int phase,
     const double *__restrict__ b, double *__restrict__ x) {
   constexpr int NB = 64, NCH = NB / CW;
   static_assert(NB % CW == 0, "chunks tile the block");
@@ -422,66 +424,73 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
   // ---- forward: L y = b, column layout: (i, j) at C[j*kd + i] ----
   // chain lane i reads (j0+i, j0+c) at j0*ld + c*kd + i; row i of the
   // off-diagonal block reads (i, j0+c) at j0*ld + c*kd + (i - j0)
-  if (chainw) {
-    load_cols<T, CW>(buf, Cr, lane, kd, 0);
-  } else if (t < kd && 64 + t < np) {
-    load_cols<T, CW>(buf, Cr, 64 + t, kd, 0);
-  }
-  __syncthreads();
-  for (int bk = 0; bk < nblk; ++bk) {
-    const int j0 = bk * NB;
-    const int64_t jb = (int64_t)j0 * ld;
+  if (phase != 2) {
     if (chainw) {
-      W xi = xs[j0 + lane];
-      W dd = 0;
-#pragma unroll
-      for (int h = 0; h < NCH; ++h) {
-        if (h > 0) load_cols<T, CW>(buf, Cr, jb + lane, kd, h * CW);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int cc = 0; cc < CW; ++cc) {
-          const int c = h * CW + cc;
-          dd = (c == lane) ? (W)buf[cc] : dd;
-          buf[cc] = (c < lane && lane - c <= kd) ? buf[cc] : (T)0;
-        }
-#pragma unroll
-        for (int cc = 0; cc < CW; ++cc) {
-          const int c = h * CW + cc;
-          const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
-          xi = fma(-(W)buf[cc], yc, xi);
-        }
-      }
-      xs[j0 + lane] = xi * dd;
-      if (bk + 1 < nblk) load_cols<T, CW>(buf, Cr, jb + (int64_t)NB * ld + lane, kd, 0);
+      load_cols<T, CW>(buf, Cr, lane, kd, 0);
+    } else if (t < kd && 64 + t < np) {
+      load_cols<T, CW>(buf, Cr, 64 + t, kd, 0);
     }
     __syncthreads();
-    if (!chainw) {
-      const int i = j0 + NB + t;
-      if (t < kd && i < np) {
-        const int cmin = i - j0 - kd;  // columns c < cmin lie outside the band
-        W acc = 0;
+    for (int bk = 0; bk < nblk; ++bk) {
+      const int j0 = bk * NB;
+      const int64_t jb = (int64_t)j0 * ld;
+      if (chainw) {
+        W xi = xs[j0 + lane];
+        W dd = 0;
 #pragma unroll
         for (int h = 0; h < NCH; ++h) {
-          if (h > 0) load_cols<T, CW>(buf, Cr, jb + (i - j0), kd, h * CW);
+          if (h > 0) load_cols<T, CW>(buf, Cr, jb + lane, kd, h * CW);
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int cc = 0; cc < CW; ++cc) {
             const int c = h * CW + cc;
-            acc = fma(c >= cmin ? (W)buf[cc] : (W)0, xs[j0 + c], acc);
+            dd = (c == lane) ? (W)buf[cc] : dd;
+            buf[cc] = (c < lane && lane - c <= kd) ? buf[cc] : (T)0;
+          }
+#pragma unroll
+          for (int cc = 0; cc < CW; ++cc) {
+            const int c = h * CW + cc;
+            const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
+            xi = fma(-(W)buf[cc], yc, xi);
           }
         }
-        xs[i] -= acc;
+        xs[j0 + lane] = xi * dd;
+        if (bk + 1 < nblk) load_cols<T, CW>(buf, Cr, jb + (int64_t)NB * ld + lane, kd, 0);
       }
-      if (bk + 1 < nblk && t < kd && i + NB < np)
-        load_cols<T, CW>(buf, Cr, jb + (int64_t)NB * ld + (i - j0), kd, 0);
+      __syncthreads();
+      if (!chainw) {
+        const int i = j0 + NB + t;
+        if (t < kd && i < np) {
+          const int cmin = i - j0 - kd;  // columns c < cmin lie outside the band
+          W acc = 0;
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) {
+            if (h > 0) load_cols<T, CW>(buf, Cr, jb + (i - j0), kd, h * CW);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int cc = 0; cc < CW; ++cc) {
+              const int c = h * CW + cc;
+              acc = fma(c >= cmin ? (W)buf[cc] : (W)0, xs[j0 + c], acc);
+            }
+          }
+          xs[i] -= acc;
+        }
+        if (bk + 1 < nblk && t < kd && i + NB < np)
+          load_cols<T, CW>(buf, Cr, jb + (int64_t)NB * ld + (i - j0), kd, 0);
+      }
+      __syncthreads();
     }
-    __syncthreads();
+  }
+  if (phase == 1) {
+    for (int i = tid; i < n; i += kWideNT) x[s.dof_off + i] = (double)xs[i];
+    return;
   }
 
   // ---- backward: L^T x = y, row layout: (i, j) at R[i*ld + (i - j)] ----
   // chain lane i reads (j0+c, j0+i) at j0*ld + c*(ld+1) - i; row i < j0
   // reads (j0+c, i) at j0*ld + c*(ld+1) + (j0 - i).  Chunks are taken from
   // the last columns down, the order of the chain.
+  __syncthreads();
   {
     const int j0 = (nblk - 1) * NB;
     const int64_t jb = (int64_t)j0 * ld;
@@ -544,21 +553,165 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
 }
 
 template <typename T, typename W, int CW>
-void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x) {
+void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x,
+                       const int *order, int count, int phase) {
+  if (count <= 0) return;
   const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
   static std::once_flag attr_once;  // per instantiation (LDS limit is per device)
   std::call_once(attr_once, [&] {
     hipFuncSetAttribute((const void *)k_band_solve_wide<T, W, CW>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
   });
-  k_band_solve_wide<T, W, CW><<<p->n_sub, kWideNT, lds, p->stream>>>(
-      p->subs_d, p->order_d, C, R, p->fac_entries + band_pad_back(p->max_kd), b, x);
+  k_band_solve_wide<T, W, CW><<<count, kWideNT, lds, p->stream>>>(
+      p->subs_d, order, C, R, p->fac_entries + band_pad_back(p->max_kd), phase, b, x);
+}
+
+// ---------------------------------------------------------------------------
+// Dissected interiors.  With halves a, b and separator plane S the interior
+// block is [A_a 0 B_a; 0 A_b B_b; B_a^T B_b^T C] and its Cholesky factor is
+// [L_a 0 0; 0 L_b 0; W_a^T W_b^T L_S] with W_h = L_h^{-1} B_h and
+// L_S L_S^T = C - W_a^T W_a - W_b^T W_b.  B_h is nonzero only in the last ns
+// rows of half h (the plane next to S), and so is W_h.
+// ---------------------------------------------------------------------------
+
+// W_h = L_h,tail^{-1} B_h in place (B_h as assembled), one thread per column;
+// uses the true-diagonal factor, before the solve layouts are built.
+__global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ subs,
+                                                  const SepDesc *__restrict__ seps,
+                                                  const double *__restrict__ fac,
+                                                  double *__restrict__ W) {
+  const SepDesc sd = seps[blockIdx.y >> 1];
+  const int h = blockIdx.y & 1;
+  const SubDesc leaf = subs[h ? sd.b : sd.a];
+  const int ns = sd.ns, ld = leaf.kd + 1, t0 = leaf.n - ns;
+  const double *L = fac + leaf.fac_off;
+  double *Wh = W + sd.w_off + (int64_t)h * ns * ns;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= ns) return;
+  for (int q = 0; q < ns; ++q) {
+    const int r = t0 + q;
+    double acc = Wh[(int64_t)q * ns + j];
+    for (int pp = 0; pp < q; ++pp) {
+      const int c = t0 + pp;  // row r, column c: L[c*ld + (r - c)]
+      acc = fma(-L[(int64_t)c * ld + (r - c)], Wh[(int64_t)pp * ns + j], acc);
+    }
+    Wh[(int64_t)q * ns + j] = acc / L[(int64_t)r * ld];
+  }
+}
+
+// Separator block (band storage with kd = ns - 1, C as assembled) minus
+// W_a^T W_a + W_b^T W_b, lower triangle; 32x32 output tiles.
+__global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ subs,
+                                                  const SepDesc *__restrict__ seps,
+                                                  const double *__restrict__ W,
+                                                  double *__restrict__ fac) {
+  const SepDesc sd = seps[blockIdx.y];
+  const int ns = sd.ns;
+  const int nt = (ns + 31) / 32;
+  // blockIdx.x enumerates the lower-triangle tiles (tq >= tp)
+  int tq = 0, rem = blockIdx.x;
+  while (rem > tq) { rem -= tq + 1; ++tq; }
+  const int tp = rem;
+  if (tq >= nt) return;
+  const SubDesc S = subs[sd.s];
+  const int ld = S.kd + 1;
+  __shared__ double Aq[32][33], Ap[32][33];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int h = 0; h < 2; ++h) {
+    const double *Wh = W + sd.w_off + (int64_t)h * ns * ns;
+    for (int k0 = 0; k0 < ns; k0 += 32) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+        const int kk = e >> 5, c = e & 31, k = k0 + kk;
+        const int q = tq * 32 + c, pcol = tp * 32 + c;
+        Aq[kk][c] = (k < ns && q < ns) ? Wh[(int64_t)k * ns + q] : 0.0;
+        Ap[kk][c] = (k < ns && pcol < ns) ? Wh[(int64_t)k * ns + pcol] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int kk = 0; kk < 32; ++kk)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+            acc[a][c] = fma(Aq[kk][ty * 2 + a], Ap[kk][tx * 2 + c], acc[a][c]);
+    }
+  }
+  double *band = fac + S.fac_off;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int q = tq * 32 + ty * 2 + a, pcol = tp * 32 + tx * 2 + c;
+      if (q < ns && pcol <= q) band[(int64_t)pcol * ld + (q - pcol)] -= acc[a][c];
+    }
+}
+
+// x_S = b_S - W_a^T y_a,tail - W_b^T y_b,tail (y in x); 64 columns per block,
+// rows split over the four wavefronts and summed in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sep_rhs(const SubDesc *__restrict__ subs,
+                                                 const SepDesc *__restrict__ seps,
+                                                 const T *__restrict__ W,
+                                                 const double *__restrict__ b,
+                                                 double *__restrict__ x) {
+  const SepDesc sd = seps[blockIdx.y];
+  const int ns = sd.ns;
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int wv = threadIdx.x >> 6;
+  __shared__ double part[4][64];
+  double acc = 0.0;
+  if (j < ns) {
+    for (int h = 0; h < 2; ++h) {
+      const SubDesc leaf = subs[h ? sd.b : sd.a];
+      const double *y = x + leaf.dof_off + leaf.n - ns;
+      const T *Wh = W + sd.w_off + (int64_t)h * ns * ns;
+      for (int i = wv; i < ns; i += 4) acc = fma((double)Wh[(int64_t)i * ns + j], y[i], acc);
+    }
+  }
+  part[wv][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (wv == 0 && j < ns) {
+    const SubDesc S = subs[sd.s];
+    const double sum = (part[0][threadIdx.x] + part[1][threadIdx.x]) +
+                       (part[2][threadIdx.x] + part[3][threadIdx.x]);
+    x[S.dof_off + j] = b[S.dof_off + j] - sum;
+  }
+}
+
+// y_h,tail -= W_h x_S, one wavefront per tail row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sep_update(const SubDesc *__restrict__ subs,
+                                                    const SepDesc *__restrict__ seps,
+                                                    const T *__restrict__ W,
+                                                    double *__restrict__ x) {
+  const SepDesc sd = seps[blockIdx.y >> 1];
+  const int h = blockIdx.y & 1;
+  const int ns = sd.ns;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= ns) return;
+  const SubDesc leaf = subs[h ? sd.b : sd.a];
+  const SubDesc S = subs[sd.s];
+  const T *row = W + sd.w_off + (int64_t)h * ns * ns + (int64_t)i * ns;
+  const double *xs = x + S.dof_off;
+  double acc = 0.0;
+  for (int j = lane; j < ns; j += 64) acc = fma((double)row[j], xs[j], acc);
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+  if (lane == 0) x[leaf.dof_off + leaf.n - ns + i] -= acc;
+}
+
+__global__ void k_f64_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
 }
 
 template <int NT, int RPT>
-void chol_launch(edd_problem *p) {
-  k_band_cholesky<32, NT, 64, RPT><<<p->n_sub, NT, 0, p->stream>>>(
-      p->subs_d, p->order_d, p->fac64_d, p->info_d);
+void chol_launch(edd_problem *p, const int *order, int count) {
+  if (count <= 0) return;
+  k_band_cholesky<32, NT, 64, RPT><<<count, NT, 0, p->stream>>>(
+      p->subs_d, order, p->fac64_d, p->info_d);
 }
 
 template <typename T, typename W, int NT>
@@ -569,7 +722,7 @@ void solve_launch(edd_problem *p, const T *C, const T *R, const double *b, doubl
     hipFuncSetAttribute((const void *)k_band_solve<T, W, NT>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
   });
-  k_band_solve<T, W, NT><<<p->n_sub, NT, lds, p->stream>>>(p->subs_d, p->order_d,
+  k_band_solve<T, W, NT><<<p->n_blk, NT, lds, p->stream>>>(p->subs_d, p->order_d,
                                                           C, R, b, x);
 }
 
@@ -585,21 +738,41 @@ size_t band_solve_lds_bytes(const edd_problem *p, int precision) {
   return ((8 * (size_t)p->max_np + 15) / 16) * 16;
 }
 
+static void cholesky_subset(edd_problem *p, const int *order, int count) {
+  const int rows = 32 + p->max_kd;  // window rows
+  if (rows <= 64) chol_launch<64, 1>(p, order, count);
+  else if (rows <= 128) chol_launch<128, 1>(p, order, count);
+  else if (rows <= 256) chol_launch<128, 2>(p, order, count);
+  else if (rows <= 512) chol_launch<256, 2>(p, order, count);
+  else chol_launch<1024, 1>(p, order, count);  // kd <= 992 (checked at setup)
+}
+
+// Factor every band block; for dissected interiors the halves first, then
+// W_h and the separator's Schur complement, then the separator.
 void launch_band_cholesky(edd_problem *p) {
   KTimer kt(p, EDD_KT_BAND_CHOLESKY);
-  const int rows = 32 + p->max_kd;  // window rows
-  if (rows <= 64) chol_launch<64, 1>(p);
-  else if (rows <= 128) chol_launch<128, 1>(p);
-  else if (rows <= 256) chol_launch<128, 2>(p);
-  else if (rows <= 512) chol_launch<256, 2>(p);
-  else chol_launch<1024, 1>(p);  // kd <= 992 (checked at setup)
+  const int nleaf = p->n_blk - p->n_sep;
+  cholesky_subset(p, p->order_leaf_d, nleaf);
+  if (p->n_sep > 0) {
+    int maxns = 0;
+    for (const SepDesc &sd : p->seps) maxns = std::max(maxns, sd.ns);
+    k_sep_trsm<<<dim3((maxns + 255) / 256, 2 * p->n_sep), 256, 0, p->stream>>>(
+        p->subs_d, p->seps_d, p->fac64_d, p->W64_d);
+    const int nt = (maxns + 31) / 32;
+    k_sep_syrk<<<dim3(nt * (nt + 1) / 2, p->n_sep), 256, 0, p->stream>>>(
+        p->subs_d, p->seps_d, p->W64_d, p->fac64_d);
+    cholesky_subset(p, p->order_sep_d, p->n_sep);
+  }
 }
 
 // After the factorisation: build the solve layouts (FP64 always, FP32 when
 // requested).  The FP64 column layout overwrites the factor in place.
 void launch_band_layouts(edd_problem *p) {
   KTimer kt(p, EDD_KT_LAYOUTS);
-  dim3 grid(64, p->n_sub);
+  dim3 grid(64, p->n_blk);
+  if (p->n_sep > 0 && p->W32_d)
+    k_f64_to_f32<<<(unsigned)((p->w_entries + 255) / 256), 256, 0, p->stream>>>(
+        p->w_entries, p->W64_d, p->W32_d);
   if (p->fac32_d)
     k_solve_layouts<float><<<grid, 256, 0, p->stream>>>(p->subs_d, p->fac64_d,
                                                         p->fac32_d, p->rac32_d);
@@ -614,9 +787,27 @@ void launch_band_layouts(edd_problem *p) {
 //            threads, 16 / 32 (FP64) or 32 / 64 (FP32) columns per load chunk
 //   0        the default choice from the half bandwidth
 bool band_solve_variant_ok(const edd_problem *p, int v) {
-  if (v >= 1 && v <= 3) return true;
+  if (v >= 1 && v <= 3) return p->n_sep == 0;  // no sweep phases
   if (v == 4 || v == 5) return p->max_kd <= kWideRows;
   return v == 0;
+}
+
+// Dissected interiors: forward sweeps of all halves and whole interiors,
+// the separator right-hand sides, the separator solves, the tail updates,
+// then the backward sweeps.
+template <typename T, int CW>
+static void solve_dissected(edd_problem *p, const T *C, const T *R, const T *W,
+                            const double *b, double *x) {
+  const int nleaf = p->n_blk - p->n_sep;
+  int maxns = 0;
+  for (const SepDesc &sd : p->seps) maxns = std::max(maxns, sd.ns);
+  solve_wide_launch<T, double, CW>(p, C, R, b, x, p->order_leaf_d, nleaf, 1);
+  k_sep_rhs<T><<<dim3((maxns + 63) / 64, p->n_sep), 256, 0, p->stream>>>(p->subs_d, p->seps_d,
+                                                                       W, b, x);
+  solve_wide_launch<T, double, CW>(p, C, R, x, x, p->order_sep_d, p->n_sep, 0);
+  k_sep_update<T><<<dim3((maxns + 3) / 4, 2 * p->n_sep), 256, 0, p->stream>>>(
+      p->subs_d, p->seps_d, W, x);
+  solve_wide_launch<T, double, CW>(p, C, R, x, x, p->order_leaf_d, nleaf, 2);
 }
 
 void launch_band_solve(edd_problem *p, int precision, const double *b,
@@ -624,7 +815,17 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
   KTimer kt(p, precision == EDD_F32 ? EDD_KT_BAND_SOLVE32 : EDD_KT_BAND_SOLVE);
   const bool f32 = precision == EDD_F32;
   int v = p->solve_variant[f32 ? 1 : 0];
-  if (v == 0) v = p->max_kd <= 64 ? 1 : (p->max_kd <= kWideRows ? 5 : 3);
+  if (v == 0) v = p->max_kd <= 64 && p->n_sep == 0 ? 1 : (p->max_kd <= kWideRows ? 5 : 3);
+  if (p->n_sep > 0) {
+    if (f32) {
+      if (v == 4) solve_dissected<float, 32>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+      else solve_dissected<float, 64>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+    } else {
+      if (v == 4) solve_dissected<double, 16>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+      else solve_dissected<double, 32>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+    }
+    return;
+  }
   // FP32 factor entries use FP64 right-hand sides and accumulation: the error
   // is then a fixed perturbation of K_II rather than arithmetic noise, which
   // the Schur complement of smooth interface vectors (a small difference of
@@ -635,8 +836,8 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
       case 1: solve_launch<float, double, 64>(p, C, R, b, x); break;
       case 2: solve_launch<float, double, 256>(p, C, R, b, x); break;
       case 3: solve_launch<float, double, 512>(p, C, R, b, x); break;
-      case 4: solve_wide_launch<float, double, 32>(p, C, R, b, x); break;
-      default: solve_wide_launch<float, double, 64>(p, C, R, b, x); break;
+      case 4: solve_wide_launch<float, double, 32>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      default: solve_wide_launch<float, double, 64>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
     }
   } else {
     const double *C = p->fac64_d, *R = p->rac64_d;
@@ -644,8 +845,8 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
       case 1: solve_launch<double, double, 64>(p, C, R, b, x); break;
       case 2: solve_launch<double, double, 256>(p, C, R, b, x); break;
       case 3: solve_launch<double, double, 512>(p, C, R, b, x); break;
-      case 4: solve_wide_launch<double, double, 16>(p, C, R, b, x); break;
-      default: solve_wide_launch<double, double, 32>(p, C, R, b, x); break;
+      case 4: solve_wide_launch<double, double, 16>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      default: solve_wide_launch<double, double, 32>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
     }
   }
 }

@@ -130,15 +130,55 @@ __global__ __launch_bounds__(kBlock) void k_apply(
   }
 }
 
-// One thread per stored band entry (column p, offset r) of every subdomain:
+// Global coordinates of local dof p of a band block.
+__device__ inline void block_coords(const SubDesc &s, int D, int p, int (&x)[3], int &c) {
+  const int l = p / D;
+  c = p - l * D;
+  const int loc[3] = {l % s.len[0], (l / s.len[0]) % s.len[1], l / (s.len[0] * s.len[1])};
+  x[0] = x[1] = x[2] = 0;
+  for (int a = 0; a < D; ++a) x[s.ax[a]] = s.lo[s.ax[a]] + (a == 2 ? s.dir : 1) * loc[a];
+}
+
+// K entry between dof c1 of node x1 and dof c2 of node x2: the sum over the
+// elements holding both nodes of E_e K0[(a2,c2), (a1,c1)].
+template <int D>
+__device__ inline double pair_entry(const Geom &g, const double *__restrict__ K0,
+                                    const double *__restrict__ E, const int (&x1)[3], int c1,
+                                    const int (&x2)[3], int c2) {
+  constexpr int NC = (D == 3) ? 8 : 4;
+  constexpr int ND = D * NC;
+  for (int a = 0; a < D; ++a) {
+    const int df = x2[a] - x1[a];
+    if (df < -1 || df > 1) return 0.0;
+  }
+  int e0[3], e1[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a >= D) { e0[a] = 0; e1[a] = 0; continue; }
+    if (x1[a] == x2[a]) { e0[a] = x1[a] - 1; e1[a] = x1[a]; }
+    else { e0[a] = min(x1[a], x2[a]); e1[a] = e0[a]; }
+    e0[a] = max(e0[a], 0);
+    e1[a] = min(e1[a], g.nel[a] - 1);
+  }
+  double val = 0.0;
+  for (int ez = e0[2]; ez <= e1[2]; ++ez)
+    for (int ey = e0[1]; ey <= e1[1]; ++ey)
+      for (int ex = e0[0]; ex <= e1[0]; ++ex) {
+        const int a1 = corner_of(x1[0] - ex, x1[1] - ey, D == 3 ? x1[2] - ez : 0);
+        const int a2 = corner_of(x2[0] - ex, x2[1] - ey, D == 3 ? x2[2] - ez : 0);
+        const int64_t el = ex + (int64_t)g.nel[0] * (ey + (int64_t)g.nel[1] * ez);
+        val = fma(E[el], K0[(a2 * D + c2) * ND + a1 * D + c1], val);
+      }
+  return val;
+}
+
+// One thread per stored band entry (column p, offset r) of every band block:
 // K[q, p] with q = p + r, summed over the elements shared by the two nodes;
 // padding columns p >= n get an identity diagonal.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_assemble_band(
     Geom g, const double *__restrict__ K0, const double *__restrict__ E,
     const SubDesc *__restrict__ subs, double *__restrict__ fac) {
-  constexpr int NC = (D == 3) ? 8 : 4;
-  constexpr int ND = D * NC;
   const SubDesc s = subs[blockIdx.y];
   const int ld = s.kd + 1;
   const int64_t total = (int64_t)s.np * ld;
@@ -152,48 +192,35 @@ __global__ __launch_bounds__(kBlock) void k_assemble_band(
     if (p >= s.n) {
       val = r == 0 ? 1.0 : 0.0;  // identity padding rows
     } else if (q < s.n) {
-      const int l1 = p / D, c1 = p - l1 * D;
-      const int l2 = q / D, c2 = q - l2 * D;
-      int loc1[3], loc2[3];
-      loc1[0] = l1 % s.len[0];
-      loc1[1] = (l1 / s.len[0]) % s.len[1];
-      loc1[2] = l1 / (s.len[0] * s.len[1]);
-      loc2[0] = l2 % s.len[0];
-      loc2[1] = (l2 / s.len[0]) % s.len[1];
-      loc2[2] = l2 / (s.len[0] * s.len[1]);
-      int x1[3] = {0, 0, 0}, x2[3] = {0, 0, 0};
-      bool near = true;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (a >= D) continue;
-        const int gax = s.ax[a];
-        x1[gax] = s.lo[gax] + loc1[a];
-        x2[gax] = s.lo[gax] + loc2[a];
-        const int df = loc2[a] - loc1[a];
-        near = near && df >= -1 && df <= 1;
-      }
-      if (near) {
-        // candidate element origins per axis
-        int e0[3], e1[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          if (a >= D) { e0[a] = 0; e1[a] = 0; continue; }
-          if (x1[a] == x2[a]) { e0[a] = x1[a] - 1; e1[a] = x1[a]; }
-          else { e0[a] = min(x1[a], x2[a]); e1[a] = e0[a]; }
-          e0[a] = max(e0[a], 0);
-          e1[a] = min(e1[a], g.nel[a] - 1);
-        }
-        for (int ez = e0[2]; ez <= e1[2]; ++ez)
-          for (int ey = e0[1]; ey <= e1[1]; ++ey)
-            for (int ex = e0[0]; ex <= e1[0]; ++ex) {
-              const int a1 = corner_of(x1[0] - ex, x1[1] - ey, D == 3 ? x1[2] - ez : 0);
-              const int a2 = corner_of(x2[0] - ex, x2[1] - ey, D == 3 ? x2[2] - ez : 0);
-              const int64_t el = ex + (int64_t)g.nel[0] * (ey + (int64_t)g.nel[1] * ez);
-              val = fma(E[el], K0[(a2 * D + c2) * ND + a1 * D + c1], val);
-            }
-      }
+      int x1[3], x2[3], c1, c2;
+      block_coords(s, D, p, x1, c1);
+      block_coords(s, D, q, x2, c2);
+      val = pair_entry<D>(g, K0, E, x1, c1, x2, c2);
     }
     band[e] = val;
+  }
+}
+
+// Couplings of a dissected interior: B_h[i][j] = K(tail row i of half h,
+// separator dof j), written where W_h will be formed.  blockIdx.y = 2*sep + h.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_assemble_coupling(
+    Geom g, const double *__restrict__ K0, const double *__restrict__ E,
+    const SubDesc *__restrict__ subs, const SepDesc *__restrict__ seps,
+    double *__restrict__ W) {
+  const SepDesc sd = seps[blockIdx.y >> 1];
+  const int h = blockIdx.y & 1;
+  const SubDesc leaf = subs[h ? sd.b : sd.a];
+  const SubDesc sp = subs[sd.s];
+  const int ns = sd.ns;
+  double *out = W + sd.w_off + (int64_t)h * ns * ns;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)ns * ns;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ns), j = (int)(e - (int64_t)i * ns);
+    int x1[3], x2[3], c1, c2;
+    block_coords(leaf, D, leaf.n - ns + i, x1, c1);
+    block_coords(sp, D, j, x2, c2);
+    out[e] = pair_entry<D>(g, K0, E, x2, c2, x1, c1);
   }
 }
 
@@ -293,13 +320,16 @@ void launch_apply_mapped(edd_problem *p, const int *tgt, int64_t ntgt,
 
 void launch_assemble_band(edd_problem *p) {
   KTimer kt(p, EDD_KT_ASSEMBLE);
-  dim3 grid(256, p->n_sub);
+  dim3 grid(256, p->n_blk);
   if (p->g.dim == 2)
     k_assemble_band<2><<<grid, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d,
                                                         p->subs_d, p->fac64_d);
   else
     k_assemble_band<3><<<grid, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d,
                                                         p->subs_d, p->fac64_d);
+  if (p->n_sep > 0 && p->g.dim == 3)
+    k_assemble_coupling<3><<<dim3(64, 2 * p->n_sep), kBlock, 0, p->stream>>>(
+        p->g, p->K0_d, p->E_d, p->subs_d, p->seps_d, p->W64_d);
 }
 
 void launch_gather(edd_problem *p, const int *nodes, int64_t n,

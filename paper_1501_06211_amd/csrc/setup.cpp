@@ -133,50 +133,119 @@ int build_geometry(edd_problem *p, const edd_mesh_desc *d) {
     return false;
   };
 
-  // subdomain interior boxes
-  p->subs.assign(p->n_sub, SubDesc{});
-  int64_t dof_off = 0, fac_off = 0;
-  p->max_kd = 0;
-  p->max_n = 0;
+  // subdomain interior boxes; local axes shortest fastest, longest slowest
+  struct Box {
+    int lo[3], len[3], ax[3];  // len and ax by local axis
+  };
+  std::vector<Box> boxes(p->n_sub);
   for (int sz = 0; sz < nblk[2]; ++sz)
     for (int sy = 0; sy < nblk[1]; ++sy)
       for (int sx = 0; sx < nblk[0]; ++sx) {
         const int sid = sx + nblk[0] * (sy + nblk[1] * sz);
         const int b[3] = {sx, sy, sz};
-        SubDesc &s = p->subs[sid];
+        Box &bx = boxes[sid];
         int len[3];
         for (int a = 0; a < 3; ++a) {
-          if (a >= D) { s.lo[a] = 0; len[a] = 1; continue; }
+          if (a >= D) { bx.lo[a] = 0; len[a] = 1; continue; }
           int lo = p->cuts[a][b[a]], hi = p->cuts[a][b[a] + 1];
           if (is_cut[a][lo] || clamped(a, lo)) ++lo;
           if (is_cut[a][hi] || clamped(a, hi)) --hi;
-          s.lo[a] = lo;
+          bx.lo[a] = lo;
           len[a] = std::max(0, hi - lo + 1);
         }
-        // local axes: shortest fastest, longest slowest (ties by axis id)
         int ax[3] = {0, 1, 2};
         std::stable_sort(ax, ax + D, [&](int x, int y) { return len[x] < len[y]; });
         for (int a = 0; a < 3; ++a) {
-          s.ax[a] = ax[a];
-          s.len[a] = len[ax[a]];
+          bx.ax[a] = ax[a];
+          bx.len[a] = len[ax[a]];
         }
-        const int64_t nodes = (int64_t)len[0] * len[1] * len[2];
-        s.n = (int)(nodes * D);
-        int kd;
-        if (D == 2) kd = D * (s.len[0] + 1) + D - 1;
-        else kd = D * (s.len[0] * s.len[1] + s.len[0] + 1) + D - 1;
-        kd = std::max(0, std::min(kd, s.n - 1));
-        s.kd = kd;
-        s.np = std::max(64, (s.n + 63) / 64 * 64);
-        s.dof_off = dof_off;
-        s.fac_off = fac_off;
-        dof_off += s.n;
-        fac_off += (int64_t)s.np * (kd + 1);
-        p->fac_entries_real += (int64_t)s.n * (kd + 1);
-        p->max_kd = std::max(p->max_kd, kd);
-        p->max_n = std::max(p->max_n, s.n);
-        p->max_np = std::max(p->max_np, s.np);
       }
+  auto band_kd = [&](int l0, int l1, int n) {
+    int kd = D == 2 ? D * (l0 + 1) + D - 1 : D * (l0 * l1 + l0 + 1) + D - 1;
+    return std::max(0, std::min(kd, n - 1));
+  };
+  auto box_dofs = [&](const Box &bx) {
+    return (int64_t)bx.len[0] * bx.len[1] * bx.len[2] * D;
+  };
+
+  // which interiors are dissected (3D only): the separator is the middle
+  // plane across the slow axis; its dense block must fit one workgroup
+  std::vector<double> work(p->n_sub);
+  for (int i = 0; i < p->n_sub; ++i) {
+    const int64_t n = box_dofs(boxes[i]);
+    work[i] = (double)n * (band_kd(boxes[i].len[0], boxes[i].len[1], (int)n) + 1);
+  }
+  std::vector<double> sorted_work(work);
+  std::sort(sorted_work.begin(), sorted_work.end());
+  const double median = sorted_work.empty() ? 0.0 : sorted_work[sorted_work.size() / 2];
+  std::vector<char> split(p->n_sub, 0);
+  for (int i = 0; i < p->n_sub && D == 3 && p->dissect != 0; ++i) {
+    const Box &bx = boxes[i];
+    const int ns = D * bx.len[0] * bx.len[1];
+    if (bx.len[2] < 5 || ns - 1 + 32 > 1024 || ns - 1 > 960) continue;
+    const int64_t n = box_dofs(bx);
+    split[i] = p->dissect == 1 ||
+               work[i] > 1.5 * median || (p->n_sub < 64 && n >= 3000);
+  }
+
+  // band blocks, interior dofs subdomain by subdomain: [half a][half b][sep]
+  p->subs.clear();
+  p->seps.clear();
+  int64_t dof_off = 0, fac_off = 0, w_off = 0;
+  auto add_block = [&](const Box &bx, int len2, int lo2, int dir, int kind, int sep,
+                       bool dense) {
+    SubDesc s{};
+    for (int a = 0; a < 3; ++a) {
+      s.ax[a] = bx.ax[a];
+      s.len[a] = bx.len[a];
+      s.lo[a] = bx.lo[a];
+    }
+    s.len[2] = len2;
+    s.lo[bx.ax[2]] = lo2;
+    s.dir = dir;
+    s.kind = kind;
+    s.sep = sep;
+    s.n = (int)((int64_t)s.len[0] * s.len[1] * s.len[2] * D);
+    s.kd = dense ? std::max(0, s.n - 1) : band_kd(s.len[0], s.len[1], s.n);
+    s.np = std::max(64, (s.n + 63) / 64 * 64);
+    s.dof_off = dof_off;
+    s.fac_off = fac_off;
+    dof_off += s.n;
+    fac_off += (int64_t)s.np * (s.kd + 1);
+    p->subs.push_back(s);
+    return (int)p->subs.size() - 1;
+  };
+  for (int i = 0; i < p->n_sub; ++i) {
+    const Box &bx = boxes[i];
+    const int L = bx.len[2], lo2 = bx.lo[bx.ax[2]];
+    if (!split[i]) {
+      add_block(bx, L, lo2, 1, 0, -1, false);
+      continue;
+    }
+    const int mid = L / 2;
+    const int sid = (int)p->seps.size();
+    SepDesc sd{};
+    sd.a = add_block(bx, mid, lo2, 1, 1, sid, false);
+    sd.b = add_block(bx, L - mid - 1, lo2 + L - 1, -1, 1, sid, false);
+    sd.s = add_block(bx, 1, lo2 + mid, 1, 2, sid, true);
+    sd.ns = p->subs[sd.s].n;
+    sd.w_off = w_off;
+    w_off += 2 * (int64_t)sd.ns * sd.ns;
+    p->seps.push_back(sd);
+  }
+  p->n_blk = (int)p->subs.size();
+  p->n_sep = (int)p->seps.size();
+  p->w_entries = w_off;
+  p->max_kd = 0;
+  p->max_n = 0;
+  p->max_np = 0;
+  p->fac_entries_real = 0;
+  for (const SubDesc &s : p->subs) {
+    p->fac_entries_real += (int64_t)s.n * (s.kd + 1);
+    p->max_kd = std::max(p->max_kd, s.kd);
+    p->max_n = std::max(p->max_n, s.n);
+    p->max_np = std::max(p->max_np, s.np);
+  }
   p->n_idofs = dof_off;
   p->n_inodes = dof_off / D;
   p->fac_entries = fac_off;
@@ -184,14 +253,14 @@ int build_geometry(edd_problem *p, const edd_mesh_desc *d) {
   // node map, packed interior nodes, interface nodes
   std::vector<int> nmap(p->n_nodes, kDirichlet);
   p->inode.assign(p->n_inodes, -1);
-  for (int sid = 0; sid < p->n_sub; ++sid) {
-    const SubDesc &s = p->subs[sid];
+  for (const SubDesc &s : p->subs) {
     const int64_t nodes = (int64_t)s.len[0] * s.len[1] * s.len[2];
     for (int64_t l = 0; l < nodes; ++l) {
       const int loc[3] = {(int)(l % s.len[0]), (int)((l / s.len[0]) % s.len[1]),
                           (int)(l / ((int64_t)s.len[0] * s.len[1]))};
       int x[3] = {0, 0, 0};
-      for (int a = 0; a < 3; ++a) x[s.ax[a]] = s.lo[s.ax[a]] + loc[a];
+      for (int a = 0; a < 3; ++a)
+        x[s.ax[a]] = s.lo[s.ax[a]] + (a == 2 ? s.dir : 1) * loc[a];
       const int64_t node = x[0] + (int64_t)p->g.nn[0] * (x[1] + (int64_t)p->g.nn[1] * x[2]);
       nmap[node] = (int)(s.dof_off + D * l);
       p->inode[s.dof_off / D + l] = (int)node;
@@ -219,13 +288,19 @@ int build_geometry(edd_problem *p, const edd_mesh_desc *d) {
       }
   p->n_gamma = (int64_t)p->gnode.size();
 
-  // launch order: most work first
-  p->order.resize(p->n_sub);
-  std::iota(p->order.begin(), p->order.end(), 0);
-  std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) {
+  // launch orders: most work first (round-robin dispatch over the XCDs then
+  // spreads the large blocks); halves and whole interiors apart from
+  // separators, which depend on them
+  auto by_work = [&](int a, int b) {
     const SubDesc &x = p->subs[a], &y = p->subs[b];
     return (int64_t)x.n * (x.kd + 1) > (int64_t)y.n * (y.kd + 1);
-  });
+  };
+  p->order.resize(p->n_blk);
+  std::iota(p->order.begin(), p->order.end(), 0);
+  std::stable_sort(p->order.begin(), p->order.end(), by_work);
+  p->order_leaf.clear();
+  p->order_sep.clear();
+  for (int b : p->order) (p->subs[b].kind == 2 ? p->order_sep : p->order_leaf).push_back(b);
 
   element_matrix(D, p->nu, p->K0);
   p->theta_default = default_theta(p->n_sub);

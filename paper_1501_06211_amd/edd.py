@@ -56,6 +56,7 @@ class MeshDesc(ctypes.Structure):
         ("nu", ctypes.c_double),
         ("clamp_faces", ctypes.c_int),
         ("factor_precision", ctypes.c_int),
+        ("dissect", ctypes.c_int),
     ]
 
 
@@ -229,7 +230,8 @@ class Problem:
     """
 
     def __init__(self, dim, nel, cuts, nu=0.3, clamp=CLAMP_X0,
-                 factor_precision=F64 | F32, stream=None, torch_allocator=True):
+                 factor_precision=F64 | F32, stream=None, torch_allocator=True,
+                 dissect=-1):
         L = lib()
         self.dim = int(dim)
         self.device = torch.cuda.current_device()
@@ -247,6 +249,7 @@ class Problem:
         d.nu = float(nu)
         d.clamp_faces = int(clamp)
         d.factor_precision = int(factor_precision)
+        d.dissect = int(dissect)
         self.factor_precision = int(factor_precision)
         self._alloc = _TorchAllocator(self.device, self.stream) if torch_allocator else None
         h = ctypes.c_void_p()

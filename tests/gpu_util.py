@@ -13,10 +13,10 @@ def require_gpu():
         pytest.skip("no GPU")
 
 
-def make_problem(w, factor_precision=None):
+def make_problem(w, factor_precision=None, dissect=-1):
     from paper_1501_06211_amd import edd
     fp = factor_precision if factor_precision is not None else (edd.F64 | edd.F32)
-    p = edd.Problem.from_workload(w, factor_precision=fp)
+    p = edd.Problem.from_workload(w, factor_precision=fp, dissect=dissect)
     E = torch.tensor(w.E, device="cuda", dtype=torch.float64)
     p.set_element_moduli(E)
     return p

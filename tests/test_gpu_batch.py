@@ -27,7 +27,7 @@ def test_every_substitution_variant_matches_the_oracle(variant):
     require_gpu()
     from paper_1501_06211_amd import edd
     p = _wide()
-    prob = make_problem(p)
+    prob = make_problem(p, dissect=0)
     prob.set_solve_variants(variant, variant)
     perm = interior_perm(p, prob)
     KII, *_ = dd.blocks(p)
@@ -39,6 +39,33 @@ def test_every_substitution_variant_matches_the_oracle(variant):
     e32 = np.linalg.norm(x32[perm] - xr) / np.linalg.norm(xr)
     print(f"variant {variant}: FP64 {e64:.2e}, FP32 factors {e32:.2e}")
     assert e64 <= 1e-12 and e32 <= 1e-5
+    prob.close()
+
+
+@pytest.mark.parametrize("variant", [4, 5])
+def test_dissected_interiors_match_the_oracle(variant):
+    """Every interior split into two band halves and a separator plane (one
+    level of nested dissection): the same K_II^{-1} as the oracle."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _wide()
+    prob = make_problem(p, dissect=1)
+    prob.set_solve_variants(variant, variant)
+    perm = interior_perm(p, prob)
+    KII, *_ = dd.blocks(p)
+    b = np.random.default_rng(3).standard_normal(prob.n_interior_dofs)
+    xr = spla.spsolve(KII.tocsc(), b[perm])
+    x = to_np(prob.solve_interior(to_cuda(b)))
+    x32 = to_np(prob.solve_interior(to_cuda(b), precision=edd.F32))
+    xi = to_cuda(b)
+    prob.solve_interior(xi, out=xi)  # in place
+    e64 = np.linalg.norm(x[perm] - xr) / np.linalg.norm(xr)
+    e32 = np.linalg.norm(x32[perm] - xr) / np.linalg.norm(xr)
+    print(f"dissected, variant {variant}: FP64 {e64:.2e}, FP32 factors {e32:.2e}")
+    assert e64 <= 1e-12 and e32 <= 1e-5
+    assert np.array_equal(to_np(xi), x)
+    with pytest.raises(edd.EddError):
+        prob.set_solve_variants(1, 1)  # one-kernel variants have no sweep phases
     prob.close()
 
 

@@ -25,7 +25,12 @@ def _cases():
     c3w = w.cantilever3d(16, 12, 12, cuts=(np.array([0, 7, 16]), np.array([0, 12]),
                                            np.array([0, 5, 12])))
     c3w.E = 1e-3 + rng.uniform(0, 1, c3w.n_el) ** 3
-    return {"2d": c2, "3d": c3, "3d_wide": c3w, "cfg_small": w.cantilever2d_uniform_64x32()}
+    return {"2d": c2, "3d": c3, "3d_wide": c3w, "3d_dissected": c3w,
+            "cfg_small": w.cantilever2d_uniform_64x32()}
+
+
+def _make(name):
+    return make_problem(CASES[name], dissect=1 if name == "3d_dissected" else 0)
 
 
 CASES = _cases()
@@ -35,7 +40,7 @@ CASES = _cases()
 def test_apply_K_parity_and_determinism(name):
     require_gpu()
     wk = CASES[name]
-    prob = make_problem(wk)
+    prob = _make(name)
     rng = np.random.default_rng(1)
     u = rng.standard_normal(wk.ndof)
     ref = fe.apply_K_elementwise(wk, u)
@@ -47,12 +52,12 @@ def test_apply_K_parity_and_determinism(name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide"])
+@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide", "3d_dissected"])
 def test_interior_solve_parity(name):
     require_gpu()
     from paper_1501_06211_amd import edd
     wk = CASES[name]
-    prob = make_problem(wk)
+    prob = _make(name)
     gamma_check(wk, prob)
     perm = interior_perm(wk, prob)
     KII, *_ = dd.blocks(wk)
@@ -68,11 +73,11 @@ def test_interior_solve_parity(name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide"])
+@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide", "3d_dissected"])
 def test_schur_apply_parity(name):
     require_gpu()
     wk = CASES[name]
-    prob = make_problem(wk)
+    prob = _make(name)
     S = dd.schur_dense(wk)
     rng = np.random.default_rng(3)
     v = rng.standard_normal(S.shape[0])
@@ -82,13 +87,13 @@ def test_schur_apply_parity(name):
     prob.close()
 
 
-@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide", "cfg_small"])
+@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide", "3d_dissected", "cfg_small"])
 @pytest.mark.parametrize("pc", ["identity"])
 def test_solve_parity(name, pc):
     require_gpu()
     from paper_1501_06211_amd import edd
     wk = CASES[name]
-    prob = make_problem(wk)
+    prob = _make(name)
     uref = fe.solve_direct(wk)
     cref = fe.compliance(wk.f, uref)
     u, st = prob.solve(to_cuda(wk.f), tol=1e-13, maxit=5000,
@@ -139,7 +144,7 @@ def test_error_paths():
 
 
 @pytest.mark.parametrize("mode", ["mixed", "relaxed"])
-@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide"])
+@pytest.mark.parametrize("name", ["2d", "3d", "3d_wide", "3d_dissected"])
 def test_mixed_precision_solve(name, mode):
     """Reduced-precision interior factors (interface refinement, or one
     flexible CG with relaxed operator accuracy): the FP64 true residual
@@ -147,7 +152,7 @@ def test_mixed_precision_solve(name, mode):
     require_gpu()
     from paper_1501_06211_amd import edd
     wk = CASES[name]
-    prob = make_problem(wk)
+    prob = _make(name)
     uref = fe.solve_direct(wk)
     cref = fe.compliance(wk.f, uref)
     m = edd.MODE_MIXED if mode == "mixed" else edd.MODE_RELAXED
