@@ -649,33 +649,40 @@ __global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ su
 }
 
 // x_S = b_S - W_a^T y_a,tail - W_b^T y_b,tail (y in x); 64 columns per block,
-// rows split over the four wavefronts and summed in a fixed order.
+// rows split over the sixteen wavefronts and summed in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_sep_rhs(const SubDesc *__restrict__ subs,
-                                                 const SepDesc *__restrict__ seps,
-                                                 const T *__restrict__ W,
-                                                 const double *__restrict__ b,
-                                                 double *__restrict__ x) {
+__global__ __launch_bounds__(1024) void k_sep_rhs(const SubDesc *__restrict__ subs,
+                                                  const SepDesc *__restrict__ seps,
+                                                  const T *__restrict__ W,
+                                                  const double *__restrict__ b,
+                                                  double *__restrict__ x) {
+  constexpr int NWV = 16;
   const SepDesc sd = seps[blockIdx.y];
   const int ns = sd.ns;
-  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int wv = threadIdx.x >> 6;
-  __shared__ double part[4][64];
-  double acc = 0.0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
+  __shared__ double part[NWV][64];
+  double acc0 = 0.0, acc1 = 0.0;
   if (j < ns) {
     for (int h = 0; h < 2; ++h) {
       const SubDesc leaf = subs[h ? sd.b : sd.a];
       const double *y = x + leaf.dof_off + leaf.n - ns;
-      const T *Wh = W + sd.w_off + (int64_t)h * ns * ns;
-      for (int i = wv; i < ns; i += 4) acc = fma((double)Wh[(int64_t)i * ns + j], y[i], acc);
+      const T *Wh = W + sd.w_off + (int64_t)h * ns * ns + j;
+      int i = wv;
+      for (; i + NWV < ns; i += 2 * NWV) {
+        acc0 = fma((double)Wh[(int64_t)i * ns], y[i], acc0);
+        acc1 = fma((double)Wh[(int64_t)(i + NWV) * ns], y[i + NWV], acc1);
+      }
+      if (i < ns) acc0 = fma((double)Wh[(int64_t)i * ns], y[i], acc0);
     }
   }
-  part[wv][threadIdx.x & 63] = acc;
+  part[wv][lane] = acc0 + acc1;
   __syncthreads();
   if (wv == 0 && j < ns) {
     const SubDesc S = subs[sd.s];
-    const double sum = (part[0][threadIdx.x] + part[1][threadIdx.x]) +
-                       (part[2][threadIdx.x] + part[3][threadIdx.x]);
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < NWV; ++k) sum += part[k][lane];
     x[S.dof_off + j] = b[S.dof_off + j] - sum;
   }
 }
@@ -802,8 +809,8 @@ static void solve_dissected(edd_problem *p, const T *C, const T *R, const T *W,
   int maxns = 0;
   for (const SepDesc &sd : p->seps) maxns = std::max(maxns, sd.ns);
   solve_wide_launch<T, double, CW>(p, C, R, b, x, p->order_leaf_d, nleaf, 1);
-  k_sep_rhs<T><<<dim3((maxns + 63) / 64, p->n_sep), 256, 0, p->stream>>>(p->subs_d, p->seps_d,
-                                                                       W, b, x);
+  k_sep_rhs<T><<<dim3((maxns + 63) / 64, p->n_sep), 1024, 0, p->stream>>>(p->subs_d, p->seps_d,
+                                                                        W, b, x);
   solve_wide_launch<T, double, CW>(p, C, R, x, x, p->order_sep_d, p->n_sep, 0);
   k_sep_update<T><<<dim3((maxns + 3) / 4, 2 * p->n_sep), 256, 0, p->stream>>>(
       p->subs_d, p->seps_d, W, x);
