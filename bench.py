@@ -13,11 +13,14 @@ restart if that phase stalls); the JSON line reports the headline as
 ``value`` (milliseconds per step, lower is better).
 
 Also reported:
-  roofline      the batched interior substitution kernel (the dominant
-                byte stream): algorithmic bytes per launch (factor read
+  roofline      the batched interior solve (the dominant byte stream; with
+                dissected interiors it is five launches: forward sweeps,
+                separator right-hand sides, separator solves, tail updates,
+                backward sweeps, timed as one unit): algorithmic bytes per
+                call (every band entry read twice, the dissection couplings
                 twice, right-hand side in, solution out) over its average
-                launch duration, from HIP events on the solver's stream
-                during the timed steps, against 8 TB/s
+                duration, from HIP events on the solver's stream during the
+                timed steps, against 8 TB/s
   cpu_baseline  the CPU oracle on a bounded sample of the same workload
                 (40 subdomain factorisations + solves, one element-by-element
                 K apply), scaled to the whole solve
@@ -39,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # by a 1 GiB copy calibration), keyed by kernel; valid only while the kernel
 # source and the workload are the ones the counters were taken on.
 MEASURED_TRAFFIC = {
-    "k_band_solve<double>": {
+    "interior_solve<double>": {
         "source": "paper_1501_06211_amd/csrc/kernels_band.hip",
         "sha256_prefix": "98b16224928e21f9",
         "workload": "cantilever3d_simp_128x64x64",
@@ -316,10 +319,14 @@ def main():
         n_solve, t_solve = kt[name]
         if not n_solve:
             return None
-        bytes_per_launch = 2 * info["factor_entries"] * word + 16 * info["n_interior_dofs"]
+        # the dissection couplings are read twice (separator right-hand
+        # side and tail update)
+        bytes_per_launch = (2 * info["factor_entries"] * word
+                            + 2 * info["coupling_entries"] * word
+                            + 16 * info["n_interior_dofs"])
         avg_ms = t_solve / n_solve
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        kname = "k_band_solve<%s>" % ("double" if word == 8 else "float")
+        kname = "interior_solve<%s>" % ("double" if word == 8 else "float")
         return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kname, w.name),

@@ -167,6 +167,8 @@ typedef struct edd_info {
   int64_t skeleton_faces;   /* face blocks of the interface preconditioner    */
   int face_classes;         /* distinct face-block shapes                     */
   double theta_default;
+  int band_blocks;          /* band blocks after dissection (>= n_sub)         */
+  int64_t coupling_entries; /* entries of the dissection couplings W_h         */
 } edd_info;
 
 /* Fill *o with the defaults: tol 1e-8, maxit 2000, FP64, Hhat_theta with

@@ -781,6 +781,8 @@ int edd_get_info(edd_problem *p, edd_info *info) {
   info->skeleton_faces = p->n_faces;
   info->face_classes = p->n_face_classes;
   info->theta_default = p->theta_default;
+  info->band_blocks = p->n_blk;
+  info->coupling_entries = p->w_entries;
   return EDD_OK;
 }
 

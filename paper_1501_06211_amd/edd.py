@@ -109,6 +109,7 @@ class Info(ctypes.Structure):
         ("max_band", ctypes.c_int), ("max_sub_dofs", ctypes.c_int),
         ("skeleton_faces", ctypes.c_int64), ("face_classes", ctypes.c_int),
         ("theta_default", ctypes.c_double),
+        ("band_blocks", ctypes.c_int), ("coupling_entries", ctypes.c_int64),
     ]
 
     def as_dict(self):
