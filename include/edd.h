@@ -103,9 +103,11 @@ typedef struct edd_mesh_desc {
                         /* into two band blocks and a separator plane (one  */
                         /* level of nested dissection) so that more         */
                         /* workgroups share its substitution; -1: when its  */
-                        /* band work exceeds 1.5x the median or the problem */
-                        /* has few subdomains, 0: never, 1: every subdomain */
-                        /* with at least 5 planes; 2D problems never split  */
+                        /* band work exceeds 1.5x the median, or when there */
+                        /* are fewer subdomains than compute units (then    */
+                        /* every interior of >= 3000 dofs), 0: never, 1:    */
+                        /* every interior with at least 5 planes; 2D        */
+                        /* problems never split                             */
 } edd_mesh_desc;
 
 typedef struct edd_solve_opts {

@@ -597,6 +597,12 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
   p->factor_precision = d->factor_precision;
   p->dissect = d->dissect;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return EDD_EHIP; }
+  {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) ==
+            hipSuccess && cu > 0)
+      p->n_cu = cu;
+  }
   rc = build_geometry(p, d);
   if (rc) { delete p; return rc; }
   int lds = 0;

@@ -86,6 +86,7 @@ struct edd_problem {
 
   // host bookkeeping
   int dissect = -1;
+  int n_cu = 256;          // compute units of the device
   int n_blk = 0;           // band blocks (subdomains, halves and separators)
   std::vector<edd::SubDesc> subs;   // band blocks
   std::vector<int> order;  // launch order of band blocks (largest first)

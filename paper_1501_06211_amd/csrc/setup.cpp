@@ -184,8 +184,9 @@ int build_geometry(edd_problem *p, const edd_mesh_desc *d) {
     const int ns = D * bx.len[0] * bx.len[1];
     if (bx.len[2] < 5 || ns - 1 + 32 > 1024 || ns - 1 > 960) continue;
     const int64_t n = box_dofs(bx);
-    split[i] = p->dissect == 1 ||
-               work[i] > 1.5 * median || (p->n_sub < 64 && n >= 3000);
+    // more band blocks than subdomains keeps more compute units streaming
+    split[i] = p->dissect == 1 || work[i] > 1.5 * median ||
+               (p->n_sub < p->n_cu && n >= 3000);
   }
 
   // band blocks, interior dofs subdomain by subdomain: [half a][half b][sep]
