@@ -137,14 +137,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nG, const int *__restri
   for (int c = 0; c < D; ++c) y[i * D + c] = acc[c];
 }
 
-// face blocks: z_f = S^{-1} A_class^{-1} S^{-1} r_f; one workgroup per face
+// face blocks: z_f = S^{-1} A_class^{-1} S^{-1} r_f; one workgroup per face,
+// each row's sum split over four quarters of the columns (shorter dependent
+// load chains) and the quarters added in a fixed order.
+constexpr int kFaceQ = 4;
+
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_face_apply(
+__global__ __launch_bounds__(256 * kFaceQ) void k_face_apply(
     const int *__restrict__ fptr, const int *__restrict__ fnode,
     const int *__restrict__ fclass, const int64_t *__restrict__ coff,
     const double *__restrict__ inv, const double *__restrict__ S,
     const double *__restrict__ r, double *__restrict__ z) {
   __shared__ double rs[kMaxFace * D];
+  __shared__ double part[kFaceQ][kMaxFace * D];
   const int f = blockIdx.x;
   const int b0 = fptr[f], m = fptr[f + 1] - b0;
   const double *A = inv + coff[fclass[f]];
@@ -155,19 +160,31 @@ __global__ __launch_bounds__(kBlock) void k_face_apply(
     for (int c = 0; c < D; ++c) rs[i * D + c] = r[(int64_t)g * D + c] * s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+  const int q = threadIdx.x / 256;
+  const int j0 = q * m / kFaceQ, j1 = (q + 1) * m / kFaceQ;
+  for (int i = threadIdx.x % 256; i < m; i += 256) {
     double acc[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = 0.0;
-    for (int j = 0; j < m; ++j) {
+    for (int j = j0; j < j1; ++j) {
       const double a = A[(int64_t)j * m + i];  // symmetric: column j, row i
 #pragma unroll
       for (int c = 0; c < D; ++c) acc[c] = fma(a, rs[j * D + c], acc[c]);
     }
+#pragma unroll
+    for (int c = 0; c < D; ++c) part[q][i * D + c] = acc[c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
     const int g = fnode[b0 + i];
     const double s = 1.0 / S[g];
 #pragma unroll
-    for (int c = 0; c < D; ++c) z[(int64_t)g * D + c] = acc[c] * s;
+    for (int c = 0; c < D; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int qq = 0; qq < kFaceQ; ++qq) v += part[qq][i * D + c];
+      z[(int64_t)g * D + c] = v * s;
+    }
   }
 }
 
@@ -802,7 +819,7 @@ struct PC {
 
   void face_precond(const double *r, double *z) {
     if (p->n_faces)
-      k_face_apply<D><<<p->n_faces, kBlock, 0, p->stream>>>(
+      k_face_apply<D><<<p->n_faces, 256 * kFaceQ, 0, p->stream>>>(
           p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d, p->face_inv_d,
           p->skS_d, r, z);
     if (p->n_rest)

@@ -107,32 +107,58 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
 }
 
 // partials[b*m + j] = sum over the block's range of z[i] * W[j*n + i]
+// partials[b*m + j] = <z, W_j> over block b's chunk; eight vectors share
+// each reduction (wavefront shuffles, one barrier), summed in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_window_dots(
     int64_t n, int m, const double *__restrict__ W, const double *__restrict__ z,
     double *__restrict__ partials) {
-  __shared__ double red[kBlock / 64];
+  constexpr int JB = 8, NW = kBlock / 64;
+  __shared__ double red[JB][NW];
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = blockIdx.x * chunk;
   const int64_t hi = min(n, lo + chunk);
-  for (int j = 0; j < m; ++j) {
-    double acc = 0.0;
-    const double *Wj = W + (int64_t)j * n;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-      acc = fma(z[i], Wj[i], acc);
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * m + j] = s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < m; j0 += JB) {
+    const int nj = min(JB, m - j0);
+    double acc[JB];
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) acc[jj] = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const double zi = z[i];
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj)
+        if (jj < nj) acc[jj] = fma(zi, W[(int64_t)(j0 + jj) * n + i], acc[jj]);
+    }
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) {
+      double v = acc[jj];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+      if (lane == 0) red[jj][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nj) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += red[threadIdx.x][w];
+      partials[(int64_t)blockIdx.x * m + j0 + threadIdx.x] = s;
+    }
+    __syncthreads();
   }
 }
 
+// pv = z - sum_j (scal[cslot+j] / scal[dslot+j]) P_j  (m <= 256)
 __global__ __launch_bounds__(kBlock) void k_window_combine(
     int64_t n, int m, const double *__restrict__ P,
     const double *__restrict__ scal, int cslot, int dslot,
     const double *__restrict__ z, double *__restrict__ pv) {
+  __shared__ double coef[256];
+  for (int j = threadIdx.x; j < m; j += blockDim.x) coef[j] = scal[cslot + j] / scal[dslot + j];
+  __syncthreads();
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     double v = z[i];
-    for (int j = 0; j < m; ++j)
-      v = fma(-(scal[cslot + j] / scal[dslot + j]), P[(int64_t)j * n + i], v);
+    for (int j = 0; j < m; ++j) v = fma(-coef[j], P[(int64_t)j * n + i], v);
     pv[i] = v;
   }
 }
