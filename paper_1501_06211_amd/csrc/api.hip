@@ -513,7 +513,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->precision = EDD_MODE_F64;
   o->precond = EDD_PC_HTHETA;
   o->theta = 0.5;
-  o->lanczos_kmax = 4;
+  o->lanczos_kmax = 3;
   o->lanczos_tol = 0.0;
   o->inner_tol = 0.0;
   o->inner_maxit = 4;

@@ -37,7 +37,7 @@ def test_binding_struct_layout_and_defaults():
     assert sorted(edd.EXPORTS) == _declared()
     o = edd.default_opts()
     assert o.tol == 1e-8 and o.maxit == 2000 and o.precond == edd.PC_HTHETA
-    assert o.theta == 0.5 and o.lanczos_kmax == 4 and o.inner_tol == 0.0
+    assert o.theta == 0.5 and o.lanczos_kmax == 3 and o.inner_maxit == 4 and o.inner_tol == 0.0
     assert o.interface_weighting == 1
     L = edd.lib()
     assert L.edd_strerror(-5).decode().startswith("interior block")
