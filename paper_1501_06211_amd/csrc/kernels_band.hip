@@ -574,8 +574,11 @@ void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, 
 // rows of half h (the plane next to S), and so is W_h.
 // ---------------------------------------------------------------------------
 
-// W_h = L_h,tail^{-1} B_h in place (B_h as assembled), one thread per column;
-// uses the true-diagonal factor, before the solve layouts are built.
+// W_h = L_h,tail^{-1} B_h in place (B_h as assembled), from the true-diagonal
+// factor (before the solve layouts are built).  A block owns 64 columns and
+// walks the rows in 64-row blocks: the block's rows minus L(block, earlier)
+// times the finished earlier rows (64x64 tiles through LDS), then a
+// triangular solve with the diagonal tile, one thread per column.
 __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ subs,
                                                   const SepDesc *__restrict__ seps,
                                                   const double *__restrict__ fac,
@@ -586,16 +589,59 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
   const int ns = sd.ns, ld = leaf.kd + 1, t0 = leaf.n - ns;
   const double *L = fac + leaf.fac_off;
   double *Wh = W + sd.w_off + (int64_t)h * ns * ns;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ns) return;
-  for (int q = 0; q < ns; ++q) {
-    const int r = t0 + q;
-    double acc = Wh[(int64_t)q * ns + j];
-    for (int pp = 0; pp < q; ++pp) {
-      const int c = t0 + pp;  // row r, column c: L[c*ld + (r - c)]
-      acc = fma(-L[(int64_t)c * ld + (r - c)], Wh[(int64_t)pp * ns + j], acc);
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= ns) return;
+  __shared__ double Lt[64][65], Xt[64][65];
+  const int tid = threadIdx.x, col = tid & 63, rg = tid >> 6;  // rows rg*16 .. +16
+  // L(t0 + a, t0 + b) for a >= b, 0 otherwise
+  auto Lat = [&](int a, int b) -> double {
+    if (a < b || a >= ns || b >= ns) return 0.0;
+    const int r = t0 + a, c = t0 + b;
+    return L[(int64_t)c * ld + (r - c)];
+  };
+  const int nrb = (ns + 63) / 64;
+  for (int qb = 0; qb < nrb; ++qb) {
+    const int q0 = qb * 64;
+    double acc[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int q = q0 + rg * 16 + a, j = c0 + col;
+      acc[a] = (q < ns && j < ns) ? Wh[(int64_t)q * ns + j] : 0.0;
     }
-    Wh[(int64_t)q * ns + j] = acc / L[(int64_t)r * ld];
+    for (int pb = 0; pb < qb; ++pb) {
+      const int p0 = pb * 64;
+      __syncthreads();
+      for (int e2 = tid; e2 < 64 * 64; e2 += 256) {
+        const int a = e2 >> 6, b = e2 & 63;
+        Lt[a][b] = Lat(q0 + a, p0 + b);
+        const int pr = p0 + a, j = c0 + b;
+        Xt[a][b] = (pr < ns && j < ns) ? Wh[(int64_t)pr * ns + j] : 0.0;
+      }
+      __syncthreads();
+      for (int b = 0; b < 64; ++b) {
+        const double x = Xt[b][col];
+#pragma unroll
+        for (int a = 0; a < 16; ++a) acc[a] = fma(-Lt[rg * 16 + a][b], x, acc[a]);
+      }
+    }
+    __syncthreads();
+    for (int e2 = tid; e2 < 64 * 64; e2 += 256) {
+      const int a = e2 >> 6, b = e2 & 63;
+      Lt[a][b] = Lat(q0 + a, q0 + b);
+    }
+#pragma unroll
+    for (int a = 0; a < 16; ++a) Xt[rg * 16 + a][col] = acc[a];
+    __syncthreads();
+    if (tid < 64) {
+      const int j = c0 + tid;
+      for (int a = 0; a < 64 && q0 + a < ns; ++a) {
+        double v = Xt[a][tid];
+        for (int b = 0; b < a; ++b) v = fma(-Lt[a][b], Xt[b][tid], v);
+        v /= Lt[a][a];
+        Xt[a][tid] = v;
+        if (j < ns) Wh[(int64_t)(q0 + a) * ns + j] = v;
+      }
+    }
   }
 }
 
@@ -763,7 +809,7 @@ void launch_band_cholesky(edd_problem *p) {
   if (p->n_sep > 0) {
     int maxns = 0;
     for (const SepDesc &sd : p->seps) maxns = std::max(maxns, sd.ns);
-    k_sep_trsm<<<dim3((maxns + 255) / 256, 2 * p->n_sep), 256, 0, p->stream>>>(
+    k_sep_trsm<<<dim3((maxns + 63) / 64, 2 * p->n_sep), 256, 0, p->stream>>>(
         p->subs_d, p->seps_d, p->fac64_d, p->W64_d);
     const int nt = (maxns + 31) / 32;
     k_sep_syrk<<<dim3(nt * (nt + 1) / 2, p->n_sep), 256, 0, p->stream>>>(
