@@ -69,9 +69,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="3d",
-                    choices=["3d", "2d", "small", "batch"],
+                    choices=["3d", "2d", "small", "batch", "sequence"],
                     help="batch: the 64 uneven problems solved concurrently "
-                         "(solves/s and per-problem latency)")
+                         "(solves/s and per-problem latency); sequence: a 3D "
+                         "128x64x64 density sequence, network trained on the "
+                         "first solves, held-out solves timed plain vs learned")
+    ap.add_argument("--train", type=int, default=40, help="sequence: training solves")
+    ap.add_argument("--test", type=int, default=20, help="sequence: held-out solves")
+    ap.add_argument("--epochs", type=int, default=20, help="sequence: training epochs")
     ap.add_argument("--precond", default="htheta", choices=["identity", "htheta"])
     ap.add_argument("--headline", default="plain",
                     choices=["plain", "mixed", "relaxed"])
@@ -259,8 +264,101 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+def run_sequence(args):
+    """Topology-optimisation-like sequence on the 3D 128x64x64 cantilever:
+    densities blended 10% per step toward a fresh seeded field and
+    thresholded (E = 1e-3 + rho^3).  The first solves (warm-started from the
+    previous solution) train the correction network; on the held-out steps
+    each solve is timed from the same warm start plain, with the learned
+    guess, and with the learned guess plus the relaxed mixed precision."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1501_06211_amd import edd, learned
+
+    torch.cuda.set_device(0)
+    base = workloads.cantilever3d_simp_128x64x64()
+    t0 = time.perf_counter()
+    seq = [torch.tensor(E, device="cuda")
+           for E in workloads.to_sequence_3d(args.train + args.test, 128, 64, 64, ell=8.0)]
+    print(f"[bench] sequence of {len(seq)} fields in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    prob = edd.Problem.from_workload(base)
+    f = torch.tensor(base.f, device="cuda")
+    prob.set_element_moduli(seq[0])
+    prob.autotune()
+    prob.cnn_setup(32)
+    prob.cnn_set_params(learned.flatten_params(
+        workloads.cnn_initial_weights(3, 4, 32, 3, seed=1)))
+    opts = dict(tol=args.tol, maxit=5000)
+    t0 = time.perf_counter()
+    tr = learned.warm_start_solves(
+        prob, f, seq[:args.train],
+        log=lambda s: print("[bench]   training " + s, file=sys.stderr, flush=True), **opts)
+    print(f"[bench] {args.train} training solves in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = learned.train(prob, tr, epochs=args.epochs, lr=1e-3,
+                         log=lambda s: print("[bench]   " + s, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    u_prev = sum(r["e"] for r in tr)
+    del tr
+    rows = []
+    for k, E in enumerate(seq[args.train:]):
+        prob.set_element_moduli(E)
+        res = {}
+        for name, extra in (("plain", {}), ("learned", {"learned_guess": 1}),
+                            ("learned_mixed", {"learned_guess": 1,
+                                               "precision": edd.MODE_RELAXED,
+                                               "mixed_inner_tol": args.switch})):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            u, st = prob.solve(f, u_prev.clone(), use_initial_guess=1, **opts, **extra)
+            torch.cuda.synchronize()
+            res[name] = (1e3 * (time.perf_counter() - t), st["iterations"], st["rel_residual"],
+                         st["learned_alpha"])
+            if name == "plain":
+                u_next = u
+        rows.append(res)
+        print(f"[bench]   held-out step {k}: " + " ".join(
+            f"{n}={v[0]:.0f}ms/{v[1]}its" for n, v in res.items()), file=sys.stderr, flush=True)
+        u_prev = u_next
+    mean = {n: float(np.mean([r[n][0] for r in rows])) for n in rows[0]}
+    its = {n: float(np.mean([r[n][1] for r in rows])) for n in rows[0]}
+    out = {
+        "metric": "time to rel.res 1e-8 on held-out steps of a 3D 128x64x64 density sequence: "
+                  "plain vs learned vs learned+mixed",
+        "value": round(mean["learned_mixed"], 2), "unit": "ms", "n_gpus": 1,
+        "steps": args.test, "warmup": 0, "ms_per_step": round(mean["learned_mixed"], 2),
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "cantilever3d_sequence_128x64x64", "train_solves": args.train,
+                   "test_solves": args.test, "epochs": args.epochs, "tol": args.tol,
+                   "parallelism": "single GPU"},
+        "mean_ms": {n: round(v, 2) for n, v in mean.items()},
+        "mean_iterations": {n: round(v, 1) for n, v in its.items()},
+        "speedup_learned_mixed_vs_plain": round(mean["plain"] / mean["learned_mixed"], 3),
+        "speedup_learned_vs_plain": round(mean["plain"] / mean["learned"], 3),
+        "training": {"seconds": round(t_train, 2), "loss_first_epoch": round(hist[0], 4),
+                     "loss_last_epoch": round(hist[-1], 4)},
+        "worst_rel_residual": max(r[n][2] for r in rows for n in r),
+    }
+    prob.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.workload == "sequence":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                              "n_gpus": args.gpus}))
+            sys.exit(2)
+        run_sequence(args)
+        return
     if args.workload == "batch":
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
