@@ -13,6 +13,7 @@
 //
 // Mixed mode: iterative refinement on the interface problem, the inner
 // interface solves using FP32 interior factors (see solve_mixed).
+#include <algorithm>
 #include <array>
 #include <atomic>
 #include <chrono>
@@ -41,6 +42,7 @@ enum : int {
   S_RES = 4,  // 4, 5: residual norms
   S_CMP = 6,  // compliance
   S_BAD = 7,
+  S_BREAK = 8,  // set on the device by a breakdown step of the interface CG
   S_C_BASE = 16,
   S_PQ_BASE = 16 + 256,
   S_PC_BASE = 16 + 512,
@@ -226,6 +228,13 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   int k = 0;
   int k_switch = -1;
   double rr_switch = 0.0;
+  // With a preconditioner that runs without host waits the host checks the
+  // residual every kCheck iterations; steps past convergence in between are
+  // harmless (a step with no descent changes nothing, see launch_cg_update).
+  constexpr int kCheck = 4;
+  const bool pc_device = pc_identity || (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0);
+  const int check = pc_device ? kCheck : 1;
+  launch_fill(p, 1, 0.0, p->scal_d + S_BREAK);
   while (std::sqrt(rr) > tol_abs) {
     if (k >= maxit) { status = EDD_NOT_CONVERGED; break; }
     // relaxed operator accuracy: once the residual is small, the S applies
@@ -259,12 +268,17 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
       const double *a[2] = {Pk, Pk}, *b[2] = {Qk, r};
       launch_dots(p, nG, 2, a, b, S_PQCUR);
     }
-    launch_cg_update(p, nG, S_PR, S_PQCUR, x, Pk, r, Qk, S_RR, S_PQ_BASE + slot);
-    rc = read_scalars(p, S_RR, 4);
-    if (rc) return rc;
+    launch_cg_update(p, nG, S_PR, S_PQCUR, x, Pk, r, Qk, S_RR, S_PQ_BASE + slot, S_BREAK);
     ++k;
+    if (k % check != 0 && k < maxit) continue;
+    rc = read_scalars(p, S_RR, 9);
+    if (rc) return rc;
     rr = p->scal_h[S_RR];
-    if (!(p->scal_h[S_PQCUR] > 0.0) || !std::isfinite(rr)) {
+    if (!std::isfinite(rr)) {
+      status = EDD_EBREAKDOWN;
+      break;
+    }
+    if (p->scal_h[S_BREAK] != 0.0 && std::sqrt(rr) > tol_abs) {
       status = EDD_EBREAKDOWN;
       break;
     }
@@ -913,11 +927,18 @@ int edd_solve_batch(edd_problem *const *ps, int n, const double *const *f_dev,
   if (nt > n) nt = n;
   std::vector<int> rcs(n, EDD_OK);
   std::vector<edd_solve_stats> st(n);
+  // largest problems first, so the longest solves are not started last
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return ps[a]->ndof * ps[a]->g.dim > ps[b]->ndof * ps[b]->g.dim;
+  });
   std::atomic<int> next{0};
   auto work = [&] {
     for (;;) {
-      const int i = next.fetch_add(1);
-      if (i >= n) break;
+      const int t = next.fetch_add(1);
+      if (t >= n) break;
+      const int i = order[t];
       if (hipSetDevice(ps[i]->device) != hipSuccess) {
         rcs[i] = EDD_EHIP;
         continue;

@@ -242,10 +242,12 @@ void launch_copy(edd_problem *p, int64_t n, const double *x, double *y);
 void launch_fill(edd_problem *p, int64_t n, double v, double *y);
 void launch_fill_f32(edd_problem *p, int64_t n, float *y);
 // x += alpha*pv; r -= alpha*q with alpha = scal[num]/scal[den]
-// also writes r.r to scal[slot] and copies scal[den] to scal[copy_dst]
+// also writes r.r to scal[slot] and copies scal[den] to scal[copy_dst];
+// a breakdown step (scal[den] <= 0, alpha not finite) changes nothing and
+// sets scal[flag_slot] = 1
 void launch_cg_update(edd_problem *p, int64_t n, int num, int den,
                       double *x, const double *pv, double *r,
-                      const double *q, int slot, int copy_dst);
+                      const double *q, int slot, int copy_dst, int flag_slot);
 void launch_reduce(edd_problem *p, int nblocks, int stride, int nout, int slot);
 size_t band_solve_lds_bytes(const edd_problem *p, int precision);
 // padding (entries) around band storage; see kernels_band.hip

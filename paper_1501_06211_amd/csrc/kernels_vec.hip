@@ -86,20 +86,33 @@ __global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double v,
 // x += alpha p, r -= alpha q with alpha = scal[num]/scal[den]; partial
 // sums of r.r for the convergence test; optionally keeps a copy of the
 // denominator (p^T S p) for the window of previous directions.
+// x += alpha p, r -= alpha q with alpha = scal[num] / scal[den].  A step
+// with scal[den] <= 0 or a non-finite alpha (breakdown, or iterations run
+// past convergence between host checks) changes nothing, stores 1 as its
+// p^T S p and raises *flag.
 __global__ __launch_bounds__(kBlock) void k_cg_update(
-    int64_t n, const double *__restrict__ scal, int num, int den,
+    int64_t n, double *__restrict__ scal, int num, int den,
     double *__restrict__ x, const double *__restrict__ pv,
     double *__restrict__ r, const double *__restrict__ q,
-    double *__restrict__ partials, double *__restrict__ copy_to) {
+    double *__restrict__ partials, double *__restrict__ copy_to,
+    double *__restrict__ flag) {
   __shared__ double red[kBlock / 64];
-  const double alpha = scal[num] / scal[den];
-  if (copy_to && blockIdx.x == 0 && threadIdx.x == 0) *copy_to = scal[den];
+  const double pq = scal[den];
+  const double alpha = scal[num] / pq;
+  const bool ok = pq > 0.0 && isfinite(alpha);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (copy_to) *copy_to = ok ? pq : 1.0;
+    if (!ok) *flag = 1.0;
+  }
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] = fma(alpha, pv[i], x[i]);
-    const double ri = fma(-alpha, q[i], r[i]);
-    r[i] = ri;
+    double ri = r[i];
+    if (ok) {
+      x[i] = fma(alpha, pv[i], x[i]);
+      ri = fma(-alpha, q[i], ri);
+      r[i] = ri;
+    }
     acc = fma(ri, ri, acc);
   }
   const double s = block_sum(acc, red);
@@ -231,11 +244,11 @@ void launch_fill_f32(edd_problem *p, int64_t n, float *y) {
 
 void launch_cg_update(edd_problem *p, int64_t n, int num, int den, double *x,
                       const double *pv, double *r, const double *q, int slot,
-                      int copy_dst) {
+                      int copy_dst, int flag_slot) {
   const unsigned g = grid_for(n);
   k_cg_update<<<g, kBlock, 0, p->stream>>>(
       n, p->scal_d, num, den, x, pv, r, q, p->partials_d,
-      copy_dst >= 0 ? p->scal_d + copy_dst : nullptr);
+      copy_dst >= 0 ? p->scal_d + copy_dst : nullptr, p->scal_d + flag_slot);
   k_reduce<<<1, kBlock, 0, p->stream>>>(p->partials_d, (int)g, 1, p->scal_d + slot);
 }
 
