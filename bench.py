@@ -44,10 +44,10 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "interior_solve<double>": {
         "source": "paper_1501_06211_amd/csrc/kernels_band.hip",
-        "sha256_prefix": "98b16224928e21f9",
+        "sha256_prefix": "7f187bc263047e41",
         "workload": "cantilever3d_simp_128x64x64",
-        "bytes": 13.517e9,
-        "profile": "profiles/hbm_counters_band_solve_cantilever3d_simp_128x64x64.md",
+        "bytes": 1.4817e+10,
+        "profile": "profiles/hbm_counters_interior_solve_cantilever3d_simp_128x64x64.md",
     },
 }
 
