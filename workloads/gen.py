@@ -94,7 +94,7 @@ def gaussian_random_field(shape, ell, seed):
         sh = [1] * len(shape)
         sh[ax] = g.size
         filt = filt * g.reshape(sh)
-    smooth = np.fft.irfftn(spec * filt, s=padded.shape)
+    smooth = np.fft.irfftn(spec * filt, s=padded.shape, axes=tuple(range(len(shape))))
     sl = tuple(slice(pad, pad + n) for n in shape)
     g = smooth[sl]
     g = (g - g.mean()) / g.std()
