@@ -84,6 +84,8 @@ def parse():
                     help="relaxed path: relative interface residual at which the "
                          "S applies move to FP32 factors")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--graphs", type=int, default=0,
+                    help="1: replay the preconditioner apply from a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (5 launches) whose "
@@ -102,9 +104,9 @@ def make_workload(name):
     return workloads.cantilever2d_uniform_64x32()
 
 
-def solve_opts(path, precond, tol, switch):
+def solve_opts(path, precond, tol, switch, graphs=0):
     from paper_1501_06211_amd import edd
-    o = dict(tol=tol, maxit=5000,
+    o = dict(tol=tol, maxit=5000, use_graphs=graphs,
              precond=edd.PC_HTHETA if precond == "htheta" else edd.PC_IDENTITY)
     if path == "mixed":
         o.update(precision=edd.MODE_MIXED)
@@ -230,7 +232,7 @@ def run_batch(args):
         fs.append(torch.tensor(wk.f, device="cuda"))
         us.append(torch.zeros(wk.ndof, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
-    opts = solve_opts(args.headline, args.precond, args.tol, args.switch)
+    opts = solve_opts(args.headline, args.precond, args.tol, args.switch, args.graphs)
     for k in range(args.warmup):
         rc, stats = edd.solve_batch(probs, fs, us, **opts)
         print(f"[bench]   warmup {k}: status {rc}", file=sys.stderr, flush=True)
@@ -252,6 +254,7 @@ def run_batch(args):
         "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": "f64" if args.headline == "plain" else "f64+f32", "data": "synthetic",
         "config": {"workload": "batch_uneven_64", "problems": len(ws), "path": args.headline,
+                   "graphs": args.graphs,
                    "precond": args.precond, "tol": args.tol, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
                        "p99": round(float(np.percentile(lat, 99)), 2),
@@ -404,7 +407,7 @@ def main():
     paths = [head] if args.no_plain else [head, other]
     for path in paths:
         ms, stats, kt = time_path(prob, E, f, u,
-                                  solve_opts(path, args.precond, args.tol, args.switch),
+                                  solve_opts(path, args.precond, args.tol, args.switch, args.graphs),
                                   args.steps, args.warmup, timing=True)
         res[path] = (ms, stats, kt)
         print(f"[bench] {path}: {ms:.1f} ms/step, its={stats[-1]['iterations']} "

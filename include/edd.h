@@ -140,6 +140,8 @@ typedef struct edd_solve_opts {
                       /* initial guess, scaled by the exact minimiser of the */
                       /* interface energy error along it (needs              */
                       /* edd_cnn_setup); 0: off                              */
+  int use_graphs;     /* 1: the device-resident preconditioner apply is      */
+                      /* captured once into a HIP graph and replayed         */
 } edd_solve_opts;
 
 typedef struct edd_solve_stats {
@@ -177,7 +179,7 @@ typedef struct edd_info {
  * theta 0.5 in the device-resident form with 3 Lanczos steps of 4 inner
  * iterations (the fastest such pair on a 1.6M-dof 3D cantilever; the
  * paper's adaptive form is lanczos_tol 1e-2, inner_tol 1e-3, Section 4), no initial guess, outer_maxit 20, mixed_inner_tol 1e-4,
- * flexible_window 0, interface_weighting 1, learned_guess 0. */
+ * flexible_window 0, interface_weighting 1, learned_guess 0, use_graphs 0. */
 void edd_default_opts(edd_solve_opts *o);
 
 /* Build a problem handle from the grid, the subdomain cuts, nu and the

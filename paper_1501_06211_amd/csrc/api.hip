@@ -537,6 +537,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->flexible_window = 0;
   o->interface_weighting = 1;
   o->learned_guess = 0;
+  o->use_graphs = 0;
 }
 
 const char *edd_strerror(int code) {
@@ -558,11 +559,14 @@ int edd_last_hip_error(edd_problem *p) { return p ? p->last_hip_error : 0; }
 int edd_destroy(edd_problem *p) {
   if (!p) return EDD_OK;
   hipStreamSynchronize(p->stream);
+  if (p->pc_graph) hipGraphExecDestroy(p->pc_graph);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   for (void *ptr : p->allocations) {
     if (p->free_fn) p->free_fn(p->alloc_ctx, ptr);
     else hipFree(ptr);
   }
   if (p->scal_h) hipHostFree(p->scal_h);
+  if (p->pc_h) hipHostFree(p->pc_h);
   kt_resolve(p);
   for (hipEvent_t e : p->kt_pool) hipEventDestroy(e);
   delete p;

@@ -58,6 +58,18 @@ struct SubDesc {
   int64_t fac_off;  // offset in band storage (entries)
 };
 
+// what a captured preconditioner graph was recorded for
+struct PcGraphKey {
+  const double *r = nullptr;
+  double *z = nullptr;
+  int k = 0, inner = 0, weighting = 0;
+  double theta = 0.0;
+  bool operator==(const PcGraphKey &o) const {
+    return r == o.r && z == o.z && k == o.k && inner == o.inner && weighting == o.weighting &&
+           theta == o.theta;
+  }
+};
+
 // A dissected interior: halves a, b and separator s (band block ids).  The
 // last ns rows of each half couple to the ns separator dofs through
 // W_h = L_h,tail^{-1} K(tail_h, S), stored row-major (tail row, separator
@@ -160,6 +172,11 @@ struct edd_problem {
   double *pc_Q_d = nullptr;     // basis vectors
   double *pc_v_d[8] = {};       // work vectors (gamma-sized)
   double *pc_h = nullptr;       // pinned host buffer for coefficients
+
+  // captured preconditioner applies (device-resident form)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t pc_graph = nullptr;
+  edd::PcGraphKey pc_graph_key;
 
   // work buffers
   double *w_I[3] = {nullptr, nullptr, nullptr};  // interior vectors

@@ -188,6 +188,14 @@ __global__ __launch_bounds__(256 * kFaceQ) void k_face_apply(
   }
 }
 
+// y = x (a kernel rather than a copy node, so captured graphs hold kernels only)
+__global__ __launch_bounds__(kBlock) void k_copy(int64_t n, const double *__restrict__ x,
+                                                 double *__restrict__ y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_rest_apply(int64_t n, const int *__restrict__ rest,
                                                        const double *__restrict__ Ld,
@@ -837,9 +845,9 @@ struct PC {
   int inner_pcg(const double *b, double *y, double tol, int maxit, int *its_out) {
     double *r = p->pc_v_d[3], *z = p->pc_v_d[4], *pv = p->pc_v_d[5], *q = p->pc_v_d[6];
     launch_fill(p, nG * D, 0.0, y);
-    hipMemcpyAsync(r, b, sizeof(double) * nG * D, hipMemcpyDeviceToDevice, p->stream);
+    k_copy<<<g1, kBlock, 0, p->stream>>>(nG * D, b, r);
     face_precond(r, z);
-    hipMemcpyAsync(pv, z, sizeof(double) * nG * D, hipMemcpyDeviceToDevice, p->stream);
+    k_copy<<<g1, kBlock, 0, p->stream>>>(nG * D, z, pv);
     cdots(2, r, z, b, b, nullptr, P_RZ, P_BB);
     int it = 0;
     for (; it < maxit; ++it) {
@@ -976,10 +984,67 @@ int apply_device(edd_problem *p, const double *r, double *z, const edd_solve_opt
   return hipGetLastError() == hipSuccess ? EDD_OK : EDD_EHIP;
 }
 
+// The device-resident apply is a fixed sequence of kernels for given
+// (r, z, k, inner steps, theta, weighting): captured once into a HIP graph
+// (on a private stream, so the caller's stream may be the null stream) and
+// replayed.  Any capture failure falls back to launching the kernels.
+template <int D>
+int apply_graph(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
+                edd_solve_stats *st) {
+  const int64_t nG = p->n_gamma;
+  const int k = std::min(o->lanczos_kmax, 32);
+  const double theta = o->theta >= 0.0 ? o->theta : p->theta_default;
+  const PcGraphKey key{r, z, k, o->inner_maxit, o->interface_weighting ? 1 : 0, theta};
+  if (!p->pc_graph || !(p->pc_graph_key == key)) {
+    if (p->pc_graph) {
+      hipGraphExecDestroy(p->pc_graph);
+      p->pc_graph = nullptr;
+    }
+    if (p->pc_kcap < k + 1) {  // allocate before capturing
+      double *Q = (double *)dev_alloc(p, sizeof(double) * nG * D * (k + 1));
+      if (!Q) return EDD_ENOMEM;
+      p->pc_Q_d = Q;
+      p->pc_kcap = k + 1;
+    }
+    if (!p->cap_stream &&
+        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      p->cap_stream = nullptr;
+      return apply_device<D>(p, r, z, o, st);
+    }
+    hipStream_t saved = p->stream;
+    const bool kt = p->kt_enabled;
+    p->kt_enabled = false;
+    p->stream = p->cap_stream;
+    hipGraph_t graph = nullptr;
+    int rc = EDD_EHIP;
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      rc = apply_device<D>(p, r, z, o, nullptr);
+      if (hipStreamEndCapture(p->cap_stream, &graph) != hipSuccess) rc = EDD_EHIP;
+    }
+    p->stream = saved;
+    p->kt_enabled = kt;
+    if (rc == EDD_OK && graph &&
+        hipGraphInstantiate(&p->pc_graph, graph, nullptr, nullptr, 0) != hipSuccess)
+      p->pc_graph = nullptr;
+    if (graph) hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!p->pc_graph) return apply_device<D>(p, r, z, o, st);
+    p->pc_graph_key = key;
+  }
+  if (hipGraphLaunch(p->pc_graph, p->stream) != hipSuccess) return EDD_EHIP;
+  if (st) {
+    st->inner_iterations += k * o->inner_maxit;
+    st->lanczos_steps += k;
+    st->precond_applications++;
+  }
+  return EDD_OK;
+}
+
 template <int D>
 int apply_t(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
             edd_solve_stats *st) {
-  if (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0) return apply_device<D>(p, r, z, o, st);
+  if (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0)
+    return o->use_graphs ? apply_graph<D>(p, r, z, o, st) : apply_device<D>(p, r, z, o, st);
   const int64_t nG = p->n_gamma;
   PC<D> pc{p, nG, (unsigned)((nG + kBlock - 1) / kBlock)};
   const double theta = o->theta >= 0.0 ? o->theta : p->theta_default;

@@ -77,6 +77,7 @@ class SolveOpts(ctypes.Structure):
         ("flexible_window", ctypes.c_int),
         ("interface_weighting", ctypes.c_int),
         ("learned_guess", ctypes.c_int),
+        ("use_graphs", ctypes.c_int),
     ]
 
 
