@@ -130,6 +130,117 @@ __global__ __launch_bounds__(kBlock) void k_apply(
   }
 }
 
+// The same K apply on a tile of nodes per block, with the tile's source
+// values (one-node halo), the moduli of the elements touching it and K0
+// staged in LDS: each source value, node-map entry and modulus is read once
+// per tile instead of once per element corner, and out-of-grid elements
+// enter with modulus zero.  TGT 0: every node, out[D node + c] (Dirichlet
+// rows 0); TGT 1: interior nodes, out[code + c]; TGT 2: interface nodes,
+// out[D gamma + c]; for TGT 1, 2 out = sy y + base[D node + c].
+template <int D>
+struct Tile;
+template <>
+struct Tile<2> {
+  static constexpr int X = 16, Y = 16, Z = 1;
+};
+template <>
+struct Tile<3> {
+  static constexpr int X = 8, Y = 8, Z = 4;
+};
+
+template <int D, int MODE, int TGT>
+__global__ __launch_bounds__(256) void k_apply_tiled(
+    Geom g, const double *__restrict__ K0, const double *__restrict__ E,
+    const int *__restrict__ nmap, Src src, const double *__restrict__ base, double sy,
+    double *__restrict__ out) {
+  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = (D == 3) ? TZ + 2 : 1;
+  constexpr int EX = TX + 1, EY = TY + 1, EZ = (D == 3) ? TZ + 1 : 1;
+  constexpr int NC = (D == 3) ? 8 : 4;
+  constexpr int ND = D * NC;
+  __shared__ double us[HX * HY * HZ * D];
+  __shared__ double Es[EX * EY * EZ];
+  __shared__ double K0s[ND * ND];
+  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY, k0 = blockIdx.z * TZ;
+  for (int q = threadIdx.x; q < ND * ND; q += 256) K0s[q] = K0[q];
+#pragma unroll 1
+  for (int q = threadIdx.x; q < HX * HY * HZ; q += 256) {
+    const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
+    const int x = i0 - 1 + hx, y = j0 - 1 + hy, z = (D == 3) ? k0 - 1 + hz : 0;
+    double v[D];
+    if (x >= 0 && x < g.nn[0] && y >= 0 && y < g.nn[1] && z >= 0 && z < g.nn[2]) {
+      fetch_node<D, MODE>(src, nmap, x + g.nn[0] * (y + g.nn[1] * z), v);
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) v[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) us[q * D + c] = v[c];
+  }
+#pragma unroll 1
+  for (int q = threadIdx.x; q < EX * EY * EZ; q += 256) {
+    const int ex = i0 - 1 + q % EX, ey = j0 - 1 + (q / EX) % EY;
+    const int ez = (D == 3) ? k0 - 1 + q / (EX * EY) : 0;
+    const bool in = ex >= 0 && ex < g.nel[0] && ey >= 0 && ey < g.nel[1] &&
+                    (D == 2 || (ez >= 0 && ez < g.nel[2]));
+    Es[q] = in ? E[ex + (int64_t)g.nel[0] * (ey + (int64_t)g.nel[1] * ez)] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+  const int i = i0 + tx, j = j0 + ty, kk = (D == 3) ? k0 + tz : 0;
+  if (i >= g.nn[0] || j >= g.nn[1] || kk >= g.nn[2]) return;
+  const int64_t node = i + (int64_t)g.nn[0] * (j + (int64_t)g.nn[1] * kk);
+  const int code = nmap[node];
+  if (TGT == 1 && code < 0) return;
+  if (TGT == 2 && (code >= 0 || code == kDirichlet)) return;
+  double yv[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) yv[c] = 0.0;
+  // one element at a time (bounded register use), K0 rows from LDS
+#pragma unroll 1
+  for (int sz = 0; sz < (D == 3 ? 2 : 1); ++sz) {
+#pragma unroll 1
+    for (int sy_ = 0; sy_ < 2; ++sy_) {
+#pragma unroll 1
+      for (int sx = 0; sx < 2; ++sx) {
+        // element (i-1+sx, j-1+sy, k-1+sz): its tile index, and this node's
+        // corner in it
+        const double Ee = Es[(tx + sx) + EX * ((ty + sy_) + EY * (D == 3 ? tz + sz : 0))];
+        const int a = corner_of(1 - sx, 1 - sy_, D == 3 ? 1 - sz : 0);
+        double xe[ND];
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+          const int hq = (tx + sx + corner_x(b)) +
+                         HX * ((ty + sy_ + corner_y(b)) +
+                               HY * (D == 3 ? tz + sz + corner_z(b) : 0));
+#pragma unroll
+          for (int c = 0; c < D; ++c) xe[D * b + c] = us[hq * D + c];
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const double *row = K0s + (a * D + c) * ND;
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < ND; ++m) acc = fma(row[m], xe[m], acc);
+          yv[c] = fma(Ee, acc, yv[c]);
+        }
+      }
+    }
+  }
+  if (TGT == 0) {
+    const bool dir = code == kDirichlet;
+#pragma unroll
+    for (int c = 0; c < D; ++c) out[(int64_t)D * node + c] = dir ? 0.0 : yv[c];
+  } else {
+    const int64_t o = TGT == 1 ? (int64_t)code : (int64_t)D * gamma_index(code);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double b0 = base ? base[(int64_t)D * node + c] : 0.0;
+      out[o + c] = fma(sy, yv[c], b0);
+    }
+  }
+}
+
 // Global coordinates of local dof p of a band block.
 __device__ inline void block_coords(const SubDesc &s, int D, int p, int (&x)[3], int &c) {
   const int l = p / D;
@@ -291,18 +402,25 @@ inline unsigned grid_for(int64_t n) {
 
 }  // namespace
 
+template <int D, int MODE, int TGT>
+void apply_tiled(edd_problem *p, const Src &s, const double *base, double sy, double *out) {
+  dim3 grid((p->g.nn[0] + Tile<D>::X - 1) / Tile<D>::X, (p->g.nn[1] + Tile<D>::Y - 1) / Tile<D>::Y,
+            (p->g.nn[2] + Tile<D>::Z - 1) / Tile<D>::Z);
+  k_apply_tiled<D, MODE, TGT><<<grid, 256, 0, p->stream>>>(p->g, p->K0_d, p->E_d, p->nmap_d,
+                                                          s, base, sy, out);
+}
+
 void launch_apply_full(edd_problem *p, const double *u, double *y) {
   KTimer kt(p, EDD_KT_APPLY_K);
   Src s{u, nullptr, nullptr, 0.0, 0.0};
-  const int64_t n = p->n_nodes;
-  if (p->g.dim == 2)
-    k_apply<2, 0><<<grid_for(n), kBlock, 0, p->stream>>>(
-        p->g, p->K0_d, p->E_d, p->nmap_d, nullptr, n, s, nullptr, 1.0, y);
-  else
-    k_apply<3, 0><<<grid_for(n), kBlock, 0, p->stream>>>(
-        p->g, p->K0_d, p->E_d, p->nmap_d, nullptr, n, s, nullptr, 1.0, y);
+  if (p->g.dim == 2) apply_tiled<2, 0, 0>(p, s, nullptr, 1.0, y);
+  else apply_tiled<3, 0, 0>(p, s, nullptr, 1.0, y);
 }
 
+// Targets are either every interior node (p->inode_d, packed interior
+// order) or every interface node (p->gnode_d, Gamma order): the tiled
+// kernel writes each through the node map.  Other target lists use the
+// node-list kernel.
 void launch_apply_mapped(edd_problem *p, const int *tgt, int64_t ntgt,
                          const double *xI, double sI, const double *xG,
                          double sG, const double *base_global, double sy,
@@ -310,12 +428,20 @@ void launch_apply_mapped(edd_problem *p, const int *tgt, int64_t ntgt,
   if (ntgt == 0) return;
   KTimer kt(p, EDD_KT_APPLY_MAPPED);
   Src s{nullptr, xI, xG, sI, sG};
-  if (p->g.dim == 2)
+  const bool D2 = p->g.dim == 2;
+  if (tgt == p->inode_d && ntgt == p->n_inodes) {
+    if (D2) apply_tiled<2, 1, 1>(p, s, base_global, sy, out);
+    else apply_tiled<3, 1, 1>(p, s, base_global, sy, out);
+  } else if (tgt == p->gnode_d && ntgt == p->n_gamma) {
+    if (D2) apply_tiled<2, 1, 2>(p, s, base_global, sy, out);
+    else apply_tiled<3, 1, 2>(p, s, base_global, sy, out);
+  } else if (D2) {
     k_apply<2, 1><<<grid_for(ntgt), kBlock, 0, p->stream>>>(
         p->g, p->K0_d, p->E_d, p->nmap_d, tgt, ntgt, s, base_global, sy, out);
-  else
+  } else {
     k_apply<3, 1><<<grid_for(ntgt), kBlock, 0, p->stream>>>(
         p->g, p->K0_d, p->E_d, p->nmap_d, tgt, ntgt, s, base_global, sy, out);
+  }
 }
 
 void launch_assemble_band(edd_problem *p) {
