@@ -19,11 +19,25 @@
 // unconditionally and out-of-band values are discarded with a select; only
 // stores are predicated.  This keeps many loads in flight per thread.
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "internal.h"
 
 namespace edd {
 namespace {
+
+// Raise a kernel's dynamic LDS limit to the device's, once per (kernel,
+// device); thread-safe.
+void set_lds_limit_once(const void *kernel, const edd_problem *p) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void *, int>> done;
+  std::lock_guard<std::mutex> lk(mu);
+  for (const auto &d : done)
+    if (d.first == kernel && d.second == p->device) return;
+  hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
+  done.emplace_back(kernel, p->device);
+}
 
 template <typename T>
 __device__ inline T lane_bcast(T v, int lane);
@@ -557,11 +571,7 @@ void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, 
                        const int *order, int count, int phase) {
   if (count <= 0) return;
   const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
-  static std::once_flag attr_once;  // per instantiation (LDS limit is per device)
-  std::call_once(attr_once, [&] {
-    hipFuncSetAttribute((const void *)k_band_solve_wide<T, W, CW>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
-  });
+  set_lds_limit_once((const void *)k_band_solve_wide<T, W, CW>, p);
   k_band_solve_wide<T, W, CW><<<count, kWideNT, lds, p->stream>>>(
       p->subs_d, order, C, R, p->fac_entries + band_pad_back(p->max_kd), phase, b, x);
 }
@@ -770,11 +780,7 @@ void chol_launch(edd_problem *p, const int *order, int count) {
 template <typename T, typename W, int NT>
 void solve_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x) {
   const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
-  static std::once_flag attr_once;  // per instantiation (LDS limit is per device)
-  std::call_once(attr_once, [&] {
-    hipFuncSetAttribute((const void *)k_band_solve<T, W, NT>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
-  });
+  set_lds_limit_once((const void *)k_band_solve<T, W, NT>, p);
   k_band_solve<T, W, NT><<<p->n_blk, NT, lds, p->stream>>>(p->subs_d, p->order_d,
                                                           C, R, b, x);
 }
