@@ -43,6 +43,7 @@ enum : int {
   S_CMP = 6,  // compliance
   S_BAD = 7,
   S_BREAK = 8,  // set on the device by a breakdown step of the interface CG
+  S_RRH = 9,    // 9..12: r.r of the last iterations (ring of kCheck)
   S_C_BASE = 16,
   S_PQ_BASE = 16 + 256,
   S_PC_BASE = 16 + 512,
@@ -235,6 +236,7 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   const bool pc_device = pc_identity || (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0);
   const int check = pc_device ? kCheck : 1;
   launch_fill(p, 1, 0.0, p->scal_d + S_BREAK);
+  int converged_at = -1;
   while (std::sqrt(rr) > tol_abs) {
     if (k >= maxit) { status = EDD_NOT_CONVERGED; break; }
     // relaxed operator accuracy: once the residual is small, the S applies
@@ -268,12 +270,22 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
       const double *a[2] = {Pk, Pk}, *b[2] = {Qk, r};
       launch_dots(p, nG, 2, a, b, S_PQCUR);
     }
-    launch_cg_update(p, nG, S_PR, S_PQCUR, x, Pk, r, Qk, S_RR, S_PQ_BASE + slot, S_BREAK);
+    launch_cg_update(p, nG, S_PR, S_PQCUR, x, Pk, r, Qk, S_RRH + (k % kCheck),
+                     S_PQ_BASE + slot, S_BREAK);
     ++k;
     if (k % check != 0 && k < maxit) continue;
-    rc = read_scalars(p, S_RR, 9);
+    rc = read_scalars(p, 0, S_RRH + kCheck);
     if (rc) return rc;
-    rr = p->scal_h[S_RR];
+    // the iterations since the last check: the first whose residual met the
+    // tolerance is the reported count (later steps only refine x)
+    const int n_chunk = (k - 1) % check + 1;
+    for (int j = 0; j < n_chunk; ++j) {
+      const int it = k - n_chunk + j;
+      const double rj = p->scal_h[S_RRH + it % kCheck];
+      if (converged_at < 0 && std::isfinite(rj) && std::sqrt(rj) <= tol_abs) converged_at = it + 1;
+    }
+    rr = p->scal_h[S_RRH + (k - 1) % kCheck];
+    if (std::sqrt(rr) > tol_abs) converged_at = -1;  // not converged at the check
     if (!std::isfinite(rr)) {
       status = EDD_EBREAKDOWN;
       break;
@@ -283,7 +295,7 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
       break;
     }
   }
-  *iters = k;
+  *iters = converged_at >= 0 ? converged_at : k;
   return status;
 }
 

@@ -190,3 +190,33 @@ def test_graph_replays_match_eager_apply():
     assert s0["iterations"] == s1["iterations"]
     assert torch.equal(u0, u1)
     prob.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_iteration_counts_match_the_oracle(dim):
+    """Same problem, same stopping rule (recursive interface residual <=
+    tol ||f||): the GPU interface CG takes the oracle's iteration count
+    within +-2, with no preconditioner (short and long recurrence) and with
+    the closed-form Hhat_theta (applied exactly by converged inverse
+    Lanczos, modulus-weighted, lumped M)."""
+    require_gpu()
+    from oracle import krylov
+    from paper_1501_06211_amd import edd
+    p = _small2d() if dim == 2 else _small3d()
+    prob = make_problem(p)
+    f = to_cuda(p.f)
+    tol = 1e-8
+    _, its_cg, _ = krylov.schur_pcg(p, precond="I", tol=tol, maxit=5000, flexible=False)
+    for window in (1, 0):
+        _, st = prob.solve(f, tol=tol, maxit=5000, precond=edd.PC_IDENTITY,
+                           flexible_window=window)
+        print(f"{dim}D identity window={window}: GPU {st['iterations']} oracle CG {its_cg}")
+        assert abs(st["iterations"] - its_cg) <= 2
+    _, its_h, _ = krylov.schur_pcg(p, precond="htilde_lumped", theta=0.5, tol=tol, maxit=2000,
+                                   weighted=True, flexible=False)
+    _, st = prob.solve(f, tol=tol, maxit=2000, precond=edd.PC_HTHETA, theta=0.5,
+                       lanczos_kmax=64, lanczos_tol=1e-14, inner_tol=1e-14, inner_maxit=2000,
+                       interface_weighting=1)
+    print(f"{dim}D Hhat_theta exact: GPU {st['iterations']} oracle PCG {its_h}")
+    assert abs(st["iterations"] - its_h) <= 2
+    prob.close()
