@@ -260,8 +260,8 @@ int edd_solve_batch(edd_problem *const *ps, int n, const double *const *f_dev,
 /* Autotuner for the batched interior substitution: times every substitution
  * variant valid for this problem's bands (1-3: one row per thread with an
  * owner wavefront per diagonal block, 64/256/512 threads per subdomain;
- * 4-5: wide bands, a dedicated chain wavefront and 1024 threads, two load
- * chunk widths) on the current factors, for FP64 and (if present) FP32
+ * 4-6: wide bands, a dedicated chain wavefront and 1024 threads, two load
+ * chunk widths, the narrower one also double-buffered) on the current factors, for FP64 and (if present) FP32
  * factors, and keeps the fastest.  Results are cached per shape class
  * (device, dimension, subdomain count, band extents) for the process;
  * force != 0 re-times.  variants (2 ints, FP64 then FP32) may be NULL.

@@ -245,7 +245,7 @@ void launch_band_layouts(edd_problem *p);
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x);
 bool band_solve_variant_ok(const edd_problem *p, int v);
-constexpr int kBandSolveVariants = 5;
+constexpr int kBandSolveVariants = 6;
 
 // kernels_vec.hip
 // dots: out[k] = sum_i a_k[i] * b_k[i] for k < nd (nd <= 4), written to

@@ -413,13 +413,15 @@ __device__ inline __amdgpu_buffer_rsrc_t band_rsrc(const T *base, int64_t entrie
 }
 
 // phase 0: both sweeps; 1: forward sweep only (y = L^{-1} b written to x);
-// 2: backward sweep only (x = L^{-T} b).
-template <typename T, typename W, int CW>
+// 2: backward sweep only (x = L^{-T} b).  With DB the load chunks are
+// double-buffered: chunk s+1 is requested before chunk s is consumed, so the
+// round trips of one block step overlap (two buffers of CW columns).
+template <typename T, typename W, int CW, bool DB>
 __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
     const SubDesc *__restrict__ subs, const int *__restrict__ order,
     const T *__restrict__ Cs, const T *__restrict__ Rs, int64_t fac_len, int phase,
     const double *__restrict__ b, double *__restrict__ x) {
-  constexpr int NB = 64, NCH = NB / CW;
+  constexpr int NB = 64, NCH = NB / CW, NBUF = DB ? 2 : 1;
   static_assert(NB % CW == 0, "chunks tile the block");
   extern __shared__ __align__(16) unsigned char smem[];
   W *xs = reinterpret_cast<W *>(smem);
@@ -433,16 +435,18 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
   const int nblk = np / NB;
 
   for (int i = tid; i < np; i += kWideNT) xs[i] = i < n ? (W)b[s.dof_off + i] : (W)0;
-  T buf[CW];
+  T buf[NBUF][CW];
 
   // ---- forward: L y = b, column layout: (i, j) at C[j*kd + i] ----
   // chain lane i reads (j0+i, j0+c) at j0*ld + c*kd + i; row i of the
-  // off-diagonal block reads (i, j0+c) at j0*ld + c*kd + (i - j0)
+  // off-diagonal block reads (i, j0+c) at j0*ld + c*kd + (i - j0).  Chunk
+  // h of a step sits in buf[h % NBUF]; chunk 0 is requested during the
+  // previous step.
   if (phase != 2) {
     if (chainw) {
-      load_cols<T, CW>(buf, Cr, lane, kd, 0);
+      load_cols<T, CW>(buf[0], Cr, lane, kd, 0);
     } else if (t < kd && 64 + t < np) {
-      load_cols<T, CW>(buf, Cr, 64 + t, kd, 0);
+      load_cols<T, CW>(buf[0], Cr, 64 + t, kd, 0);
     }
     __syncthreads();
     for (int bk = 0; bk < nblk; ++bk) {
@@ -453,23 +457,28 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
         W dd = 0;
 #pragma unroll
         for (int h = 0; h < NCH; ++h) {
-          if (h > 0) load_cols<T, CW>(buf, Cr, jb + lane, kd, h * CW);
+          T(&cur)[CW] = buf[h % NBUF];
+          if (DB) {
+            if (h + 1 < NCH) load_cols<T, CW>(buf[(h + 1) % NBUF], Cr, jb + lane, kd, (h + 1) * CW);
+          } else if (h > 0) {
+            load_cols<T, CW>(cur, Cr, jb + lane, kd, h * CW);
+          }
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int cc = 0; cc < CW; ++cc) {
             const int c = h * CW + cc;
-            dd = (c == lane) ? (W)buf[cc] : dd;
-            buf[cc] = (c < lane && lane - c <= kd) ? buf[cc] : (T)0;
+            dd = (c == lane) ? (W)cur[cc] : dd;
+            cur[cc] = (c < lane && lane - c <= kd) ? cur[cc] : (T)0;
           }
 #pragma unroll
           for (int cc = 0; cc < CW; ++cc) {
             const int c = h * CW + cc;
             const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
-            xi = fma(-(W)buf[cc], yc, xi);
+            xi = fma(-(W)cur[cc], yc, xi);
           }
         }
         xs[j0 + lane] = xi * dd;
-        if (bk + 1 < nblk) load_cols<T, CW>(buf, Cr, jb + (int64_t)NB * ld + lane, kd, 0);
+        if (bk + 1 < nblk) load_cols<T, CW>(buf[0], Cr, jb + (int64_t)NB * ld + lane, kd, 0);
       }
       __syncthreads();
       if (!chainw) {
@@ -479,18 +488,24 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
           W acc = 0;
 #pragma unroll
           for (int h = 0; h < NCH; ++h) {
-            if (h > 0) load_cols<T, CW>(buf, Cr, jb + (i - j0), kd, h * CW);
+            T(&cur)[CW] = buf[h % NBUF];
+            if (DB) {
+              if (h + 1 < NCH)
+                load_cols<T, CW>(buf[(h + 1) % NBUF], Cr, jb + (i - j0), kd, (h + 1) * CW);
+            } else if (h > 0) {
+              load_cols<T, CW>(cur, Cr, jb + (i - j0), kd, h * CW);
+            }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int cc = 0; cc < CW; ++cc) {
               const int c = h * CW + cc;
-              acc = fma(c >= cmin ? (W)buf[cc] : (W)0, xs[j0 + c], acc);
+              acc = fma(c >= cmin ? (W)cur[cc] : (W)0, xs[j0 + c], acc);
             }
           }
           xs[i] -= acc;
         }
         if (bk + 1 < nblk && t < kd && i + NB < np)
-          load_cols<T, CW>(buf, Cr, jb + (int64_t)NB * ld + (i - j0), kd, 0);
+          load_cols<T, CW>(buf[0], Cr, jb + (int64_t)NB * ld + (i - j0), kd, 0);
       }
       __syncthreads();
     }
@@ -503,15 +518,16 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
   // ---- backward: L^T x = y, row layout: (i, j) at R[i*ld + (i - j)] ----
   // chain lane i reads (j0+c, j0+i) at j0*ld + c*(ld+1) - i; row i < j0
   // reads (j0+c, i) at j0*ld + c*(ld+1) + (j0 - i).  Chunks are taken from
-  // the last columns down, the order of the chain.
+  // the last columns down (the order of the chain): step s of a block uses
+  // chunk NCH-1-s in buf[s % NBUF].
   __syncthreads();
   {
     const int j0 = (nblk - 1) * NB;
     const int64_t jb = (int64_t)j0 * ld;
     if (chainw) {
-      load_cols<T, CW>(buf, Rr, jb - lane, ld + 1, NB - CW);
+      load_cols<T, CW>(buf[0], Rr, jb - lane, ld + 1, NB - CW);
     } else if (t < kd && j0 - kd + t >= 0) {
-      load_cols<T, CW>(buf, Rr, jb + (kd - t), ld + 1, NB - CW);
+      load_cols<T, CW>(buf[0], Rr, jb + (kd - t), ld + 1, NB - CW);
     }
   }
   for (int bk = nblk - 1; bk >= 0; --bk) {
@@ -521,24 +537,30 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
       W xi = xs[j0 + lane];
       W dd = 0;
 #pragma unroll
-      for (int h = NCH - 1; h >= 0; --h) {
-        if (h < NCH - 1) load_cols<T, CW>(buf, Rr, jb - lane, ld + 1, h * CW);
+      for (int st = 0; st < NCH; ++st) {
+        const int h = NCH - 1 - st;
+        T(&cur)[CW] = buf[st % NBUF];
+        if (DB) {
+          if (st + 1 < NCH) load_cols<T, CW>(buf[(st + 1) % NBUF], Rr, jb - lane, ld + 1, (h - 1) * CW);
+        } else if (st > 0) {
+          load_cols<T, CW>(cur, Rr, jb - lane, ld + 1, h * CW);
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int cc = 0; cc < CW; ++cc) {
           const int c = h * CW + cc;
-          dd = (c == lane) ? (W)buf[cc] : dd;
-          buf[cc] = (c > lane && c - lane <= kd) ? buf[cc] : (T)0;
+          dd = (c == lane) ? (W)cur[cc] : dd;
+          cur[cc] = (c > lane && c - lane <= kd) ? cur[cc] : (T)0;
         }
 #pragma unroll
         for (int cc = CW - 1; cc >= 0; --cc) {
           const int c = h * CW + cc;
           const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
-          xi = fma(-(W)buf[cc], yc, xi);
+          xi = fma(-(W)cur[cc], yc, xi);
         }
       }
       xs[j0 + lane] = xi * dd;
-      if (bk > 0) load_cols<T, CW>(buf, Rr, jb - (int64_t)NB * ld - lane, ld + 1, NB - CW);
+      if (bk > 0) load_cols<T, CW>(buf[0], Rr, jb - (int64_t)NB * ld - lane, ld + 1, NB - CW);
     }
     __syncthreads();
     if (!chainw) {
@@ -547,32 +569,39 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
         // (j0+c, i) lies in the band for c <= kd - (j0 - i) = t
         W acc = 0;
 #pragma unroll
-        for (int h = NCH - 1; h >= 0; --h) {
-          if (h < NCH - 1) load_cols<T, CW>(buf, Rr, jb + (kd - t), ld + 1, h * CW);
+        for (int st = 0; st < NCH; ++st) {
+          const int h = NCH - 1 - st;
+          T(&cur)[CW] = buf[st % NBUF];
+          if (DB) {
+            if (st + 1 < NCH)
+              load_cols<T, CW>(buf[(st + 1) % NBUF], Rr, jb + (kd - t), ld + 1, (h - 1) * CW);
+          } else if (st > 0) {
+            load_cols<T, CW>(cur, Rr, jb + (kd - t), ld + 1, h * CW);
+          }
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int cc = 0; cc < CW; ++cc) {
             const int c = h * CW + cc;
-            acc = fma(c <= t ? (W)buf[cc] : (W)0, xs[j0 + c], acc);
+            acc = fma(c <= t ? (W)cur[cc] : (W)0, xs[j0 + c], acc);
           }
         }
         xs[i] -= acc;
       }
       if (bk > 0 && t < kd && i - NB >= 0)
-        load_cols<T, CW>(buf, Rr, jb - (int64_t)NB * ld + (kd - t), ld + 1, NB - CW);
+        load_cols<T, CW>(buf[0], Rr, jb - (int64_t)NB * ld + (kd - t), ld + 1, NB - CW);
     }
     __syncthreads();
   }
   for (int i = tid; i < n; i += kWideNT) x[s.dof_off + i] = (double)xs[i];
 }
 
-template <typename T, typename W, int CW>
+template <typename T, typename W, int CW, bool DB>
 void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x,
                        const int *order, int count, int phase) {
   if (count <= 0) return;
   const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
-  set_lds_limit_once((const void *)k_band_solve_wide<T, W, CW>, p);
-  k_band_solve_wide<T, W, CW><<<count, kWideNT, lds, p->stream>>>(
+  set_lds_limit_once((const void *)k_band_solve_wide<T, W, CW, DB>, p);
+  k_band_solve_wide<T, W, CW, DB><<<count, kWideNT, lds, p->stream>>>(
       p->subs_d, order, C, R, p->fac_entries + band_pad_back(p->max_kd), phase, b, x);
 }
 
@@ -844,29 +873,30 @@ void launch_band_layouts(edd_problem *p) {
 //            64 / 256 / 512 threads per subdomain
 //   4, 5     wide bands (kd <= kWideRows): dedicated chain wavefront, 1024
 //            threads, 16 / 32 (FP64) or 32 / 64 (FP32) columns per load chunk
+//   6        as 4 with double-buffered load chunks
 //   0        the default choice from the half bandwidth
 bool band_solve_variant_ok(const edd_problem *p, int v) {
   if (v >= 1 && v <= 3) return p->n_sep == 0;  // no sweep phases
-  if (v == 4 || v == 5) return p->max_kd <= kWideRows;
+  if (v >= 4 && v <= 6) return p->max_kd <= kWideRows;
   return v == 0;
 }
 
 // Dissected interiors: forward sweeps of all halves and whole interiors,
 // the separator right-hand sides, the separator solves, the tail updates,
 // then the backward sweeps.
-template <typename T, int CW>
+template <typename T, int CW, bool DB>
 static void solve_dissected(edd_problem *p, const T *C, const T *R, const T *W,
                             const double *b, double *x) {
   const int nleaf = p->n_blk - p->n_sep;
   int maxns = 0;
   for (const SepDesc &sd : p->seps) maxns = std::max(maxns, sd.ns);
-  solve_wide_launch<T, double, CW>(p, C, R, b, x, p->order_leaf_d, nleaf, 1);
+  solve_wide_launch<T, double, CW, DB>(p, C, R, b, x, p->order_leaf_d, nleaf, 1);
   k_sep_rhs<T><<<dim3((maxns + 63) / 64, p->n_sep), 1024, 0, p->stream>>>(p->subs_d, p->seps_d,
                                                                         W, b, x);
-  solve_wide_launch<T, double, CW>(p, C, R, x, x, p->order_sep_d, p->n_sep, 0);
+  solve_wide_launch<T, double, CW, DB>(p, C, R, x, x, p->order_sep_d, p->n_sep, 0);
   k_sep_update<T><<<dim3((maxns + 3) / 4, 2 * p->n_sep), 256, 0, p->stream>>>(
       p->subs_d, p->seps_d, W, x);
-  solve_wide_launch<T, double, CW>(p, C, R, x, x, p->order_leaf_d, nleaf, 2);
+  solve_wide_launch<T, double, CW, DB>(p, C, R, x, x, p->order_leaf_d, nleaf, 2);
 }
 
 void launch_band_solve(edd_problem *p, int precision, const double *b,
@@ -877,11 +907,13 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
   if (v == 0) v = p->max_kd <= 64 && p->n_sep == 0 ? 1 : (p->max_kd <= kWideRows ? 5 : 3);
   if (p->n_sep > 0) {
     if (f32) {
-      if (v == 4) solve_dissected<float, 32>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
-      else solve_dissected<float, 64>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+      if (v == 4) solve_dissected<float, 32, false>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+      else if (v == 6) solve_dissected<float, 32, true>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+      else solve_dissected<float, 64, false>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
     } else {
-      if (v == 4) solve_dissected<double, 16>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
-      else solve_dissected<double, 32>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+      if (v == 4) solve_dissected<double, 16, false>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+      else if (v == 6) solve_dissected<double, 16, true>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+      else solve_dissected<double, 32, false>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
     }
     return;
   }
@@ -895,8 +927,9 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
       case 1: solve_launch<float, double, 64>(p, C, R, b, x); break;
       case 2: solve_launch<float, double, 256>(p, C, R, b, x); break;
       case 3: solve_launch<float, double, 512>(p, C, R, b, x); break;
-      case 4: solve_wide_launch<float, double, 32>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
-      default: solve_wide_launch<float, double, 64>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      case 4: solve_wide_launch<float, double, 32, false>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      case 6: solve_wide_launch<float, double, 32, true>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      default: solve_wide_launch<float, double, 64, false>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
     }
   } else {
     const double *C = p->fac64_d, *R = p->rac64_d;
@@ -904,8 +937,9 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
       case 1: solve_launch<double, double, 64>(p, C, R, b, x); break;
       case 2: solve_launch<double, double, 256>(p, C, R, b, x); break;
       case 3: solve_launch<double, double, 512>(p, C, R, b, x); break;
-      case 4: solve_wide_launch<double, double, 16>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
-      default: solve_wide_launch<double, double, 32>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      case 4: solve_wide_launch<double, double, 16, false>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      case 6: solve_wide_launch<double, double, 16, true>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      default: solve_wide_launch<double, double, 32, false>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
     }
   }
 }

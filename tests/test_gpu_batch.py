@@ -22,7 +22,7 @@ def _wide():
     return p
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
 def test_every_substitution_variant_matches_the_oracle(variant):
     require_gpu()
     from paper_1501_06211_amd import edd
@@ -42,7 +42,7 @@ def test_every_substitution_variant_matches_the_oracle(variant):
     prob.close()
 
 
-@pytest.mark.parametrize("variant", [4, 5])
+@pytest.mark.parametrize("variant", [4, 5, 6])
 def test_dissected_interiors_match_the_oracle(variant):
     """Every interior split into two band halves and a separator plane (one
     level of nested dissection): the same K_II^{-1} as the oracle."""
@@ -74,7 +74,7 @@ def test_autotune_picks_valid_variants_and_caches():
     p = _wide()
     prob = make_problem(p)
     v = prob.autotune(force=True)
-    assert all(1 <= x <= 5 for x in v)
+    assert all(1 <= x <= 6 for x in v)
     prob2 = make_problem(p)
     assert prob2.autotune() == v  # same shape class: cached
     u, st = prob2.solve(to_cuda(p.f), tol=1e-12, maxit=3000)
