@@ -25,6 +25,7 @@
 #include <map>
 #include <numeric>
 #include <unordered_map>
+#include <utility>
 
 #include "internal.h"
 
@@ -194,6 +195,190 @@ __global__ __launch_bounds__(kBlock) void k_copy(int64_t n, const double *__rest
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     y[i] = x[i];
+}
+
+// ---- fused steps of the fixed-count inner PCG ------------------------------
+// q = L x with per-block partial sums of x.q per component.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t nG, const int *__restrict__ rowptr,
+                                                     const int *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ y,
+                                                     double *__restrict__ partials) {
+  __shared__ double red[kBlock / 64];
+  double dot[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) dot[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nG;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = 0.0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      const double v = val[k];
+      const int64_t j = col[k];
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] = fma(v, x[j * D + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      y[i * D + c] = acc[c];
+      dot[c] = fma(x[i * D + c], acc[c], dot[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double s = block_sum(dot[c], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * D + c] = s;
+  }
+}
+
+// The face-block preconditioner fused with the PCG update that precedes it
+// and the r.z partial sums that follow it.  Unless INIT: per component
+// a = scal[rz]/scal[pq], y += a p and r -= a q on the face's nodes (every
+// interface node is in exactly one face or in the rest set).  Then
+// z = S^{-1} A^{-1} S^{-1} r on the face; INIT also writes pdir = z.  The
+// face's sum of r.z per component goes to partials[f*D + c].
+template <int D, bool INIT>
+__global__ __launch_bounds__(256 * kFaceQ) void k_face_pcg(
+    const int *__restrict__ fptr, const int *__restrict__ fnode,
+    const int *__restrict__ fclass, const int64_t *__restrict__ coff,
+    const double *__restrict__ inv, const double *__restrict__ S,
+    const double *__restrict__ scal, int rz, int pq, double *__restrict__ y,
+    const double *__restrict__ p, double *__restrict__ r, const double *__restrict__ q,
+    double *__restrict__ z, double *__restrict__ pdir, double *__restrict__ partials) {
+  __shared__ double rs[kMaxFace * D];
+  __shared__ double rn[kMaxFace * D];
+  __shared__ double part[kFaceQ][kMaxFace * D];
+  __shared__ double red[kFaceQ * 4][D];
+  const int f = blockIdx.x;
+  const int b0 = fptr[f], m = fptr[f + 1] - b0;
+  const double *A = inv + coff[fclass[f]];
+  double a[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double den = INIT ? 0.0 : scal[pq + c];
+    a[c] = (!INIT && den != 0.0) ? scal[rz + c] / den : 0.0;
+  }
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const int64_t g = fnode[b0 + i];
+    const double s = 1.0 / S[g];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double rv = r[g * D + c];
+      if (!INIT) {
+        y[g * D + c] = fma(a[c], p[g * D + c], y[g * D + c]);
+        rv = fma(-a[c], q[g * D + c], rv);
+        r[g * D + c] = rv;
+      }
+      rn[i * D + c] = rv;
+      rs[i * D + c] = rv * s;
+    }
+  }
+  __syncthreads();
+  const int qq0 = threadIdx.x / 256;
+  const int j0 = qq0 * m / kFaceQ, j1 = (qq0 + 1) * m / kFaceQ;
+  for (int i = threadIdx.x % 256; i < m; i += 256) {
+    double acc[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+      const double av = A[(int64_t)j * m + i];  // symmetric: column j, row i
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] = fma(av, rs[j * D + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) part[qq0][i * D + c] = acc[c];
+  }
+  __syncthreads();
+  double dot[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) dot[c] = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const int64_t g = fnode[b0 + i];
+    const double s = 1.0 / S[g];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k2 = 0; k2 < kFaceQ; ++k2) v += part[k2][i * D + c];
+      const double zv = v * s;
+      z[g * D + c] = zv;
+      if (INIT) pdir[g * D + c] = zv;
+      dot[c] = fma(rn[i * D + c], zv, dot[c]);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    double v = dot[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) red[wv][c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < D) {
+    double sum = 0.0;
+    for (int w2 = 0; w2 < kFaceQ * 4; ++w2) sum += red[w2][threadIdx.x];
+    partials[(int64_t)f * D + threadIdx.x] = sum;
+  }
+}
+
+// The same for the nodes outside the faces (diagonal preconditioner);
+// partial sums at partials[(pbase + block)*D + c].
+template <int D, bool INIT>
+__global__ __launch_bounds__(kBlock) void k_rest_pcg(
+    int64_t n, const int *__restrict__ rest, const double *__restrict__ Ld,
+    const double *__restrict__ scal, int rz, int pq, double *__restrict__ y,
+    const double *__restrict__ p, double *__restrict__ r, const double *__restrict__ q,
+    double *__restrict__ z, double *__restrict__ pdir, double *__restrict__ partials,
+    int pbase) {
+  __shared__ double red[kBlock / 64];
+  double dot[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) dot[c] = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = rest[t];
+    const double s = 1.0 / Ld[g];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double rv = r[g * D + c];
+      if (!INIT) {
+        const double den = scal[pq + c];
+        const double a = den != 0.0 ? scal[rz + c] / den : 0.0;
+        y[g * D + c] = fma(a, p[g * D + c], y[g * D + c]);
+        rv = fma(-a, q[g * D + c], rv);
+        r[g * D + c] = rv;
+      }
+      const double zv = rv * s;
+      z[g * D + c] = zv;
+      if (INIT) pdir[g * D + c] = zv;
+      dot[c] = fma(rv, zv, dot[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sm = block_sum(dot[c], red);
+    if (threadIdx.x == 0) partials[(pbase + (int64_t)blockIdx.x) * D + c] = sm;
+  }
+}
+
+// p = z + (scal[rz_new]/scal[rz_old]) p per component.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_pcg_dir2(int64_t nG, const double *__restrict__ scal,
+                                                     int rz_new, int rz_old,
+                                                     const double *__restrict__ z,
+                                                     double *__restrict__ p) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nG) return;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double rzo = scal[rz_old + c];
+    const double b = rzo != 0.0 ? scal[rz_new + c] / rzo : 0.0;
+    p[i * D + c] = fma(b, p[i * D + c], z[i * D + c]);
+  }
 }
 
 template <int D>
@@ -842,7 +1027,63 @@ struct PC {
 
   // y ~ L^{-1} b (all components), relative tolerance tol; with tol <= 0
   // exactly maxit iterations run with no host synchronisation
+  // face-block preconditioner fused with the PCG update and r.z sums; the
+  // reduced sums land in scal[out_slot + c]
+  template <bool INIT>
+  void face_pcg(int rz, double *y, const double *pv, double *r, const double *q, double *z,
+                double *pdir, int out_slot) {
+    const unsigned nrb = rest_blocks();
+    if (p->n_faces)
+      k_face_pcg<D, INIT><<<p->n_faces, 256 * kFaceQ, 0, p->stream>>>(
+          p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d, p->face_inv_d,
+          p->skS_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir, p->partials_d);
+    if (p->n_rest)
+      k_rest_pcg<D, INIT><<<nrb, kBlock, 0, p->stream>>>(
+          p->n_rest, p->rest_d, p->skLdiag_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir,
+          p->partials_d, p->n_faces);
+    if (out_slot >= 0)
+      k_reduce<<<D, kBlock, 0, p->stream>>>(p->partials_d, (int)(p->n_faces + (p->n_rest ? nrb : 0)),
+                                            D, p->scal_d + out_slot);
+  }
+
+  // grids of the fused kernels (grid-stride loops, so capped); the fused
+  // path needs one partial sum per block and component
+  unsigned rest_blocks() const {
+    return (unsigned)std::min<int64_t>((p->n_rest + kBlock - 1) / kBlock, 1024);
+  }
+  unsigned spmv_blocks() const { return std::min(g1, 4096u); }
+  bool fused_fits() const {
+    const size_t need = std::max<size_t>((size_t)p->n_faces + rest_blocks(), spmv_blocks());
+    return p->n_faces + p->n_rest > 0 && need * D <= p->partials_len;
+  }
+
+  // y ~ L^{-1} b, exactly maxit PCG iterations with no host synchronisation:
+  // six launches per iteration (L apply with p.q sums, their reduction, the
+  // fused update / face blocks / r.z sums (two kernels and a reduction),
+  // the new direction); r.z alternates between two scalar slots.
+  int inner_pcg_fixed(const double *b, double *y, int maxit, int *its_out) {
+    double *r = p->pc_v_d[3], *z = p->pc_v_d[4], *pv = p->pc_v_d[5], *q = p->pc_v_d[6];
+    launch_fill(p, nG * D, 0.0, y);
+    k_copy<<<g1, kBlock, 0, p->stream>>>(nG * D, b, r);
+    face_pcg<true>(0, y, pv, r, q, z, pv, P_RZ);
+    int cur = P_RZ, nxt = P_RZN;
+    for (int it = 0; it < maxit; ++it) {
+      k_spmv_dot<D><<<spmv_blocks(), kBlock, 0, p->stream>>>(
+          nG, p->skL_rowptr_d, p->skL_col_d, p->skL_val_d, pv, q, p->partials_d);
+      k_reduce<<<D, kBlock, 0, p->stream>>>(p->partials_d, (int)spmv_blocks(), D,
+                                            p->scal_d + P_PQ);
+      const bool last = it + 1 == maxit;
+      face_pcg<false>(cur, y, pv, r, q, z, nullptr, last ? -1 : nxt);
+      if (last) break;
+      k_pcg_dir2<D><<<g1, kBlock, 0, p->stream>>>(nG, p->scal_d, nxt, cur, z, pv);
+      std::swap(cur, nxt);
+    }
+    *its_out = maxit;
+    return hipGetLastError() == hipSuccess ? EDD_OK : EDD_EHIP;
+  }
+
   int inner_pcg(const double *b, double *y, double tol, int maxit, int *its_out) {
+    if (tol <= 0.0 && fused_fits()) return inner_pcg_fixed(b, y, maxit, its_out);
     double *r = p->pc_v_d[3], *z = p->pc_v_d[4], *pv = p->pc_v_d[5], *q = p->pc_v_d[6];
     launch_fill(p, nG * D, 0.0, y);
     k_copy<<<g1, kBlock, 0, p->stream>>>(nG * D, b, r);
