@@ -69,6 +69,37 @@ def test_dissected_interiors_match_the_oracle(variant):
     prob.close()
 
 
+def _wider():
+    """Half bandwidths above 448 (most of the 960 off-diagonal threads busy)."""
+    rng = np.random.default_rng(12)
+    p = w.cantilever3d(28, 14, 14, cuts=(np.array([0, 14, 28]), np.array([0, 14]),
+                                         np.array([0, 14])))
+    p.E = 1e-3 + rng.uniform(0, 1, p.n_el) ** 3
+    return p
+
+
+@pytest.mark.parametrize("variant,dissect", [(5, 0), (6, 0), (5, 1), (6, 1)])
+def test_wide_variants_at_half_bandwidths_past_448(variant, dissect):
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _wider()
+    prob = make_problem(p, dissect=dissect)
+    assert prob.info["max_band"] > 448
+    prob.set_solve_variants(variant, variant)
+    perm = interior_perm(p, prob)
+    KII, *_ = dd.blocks(p)
+    b = np.random.default_rng(4).standard_normal(prob.n_interior_dofs)
+    xr = spla.spsolve(KII.tocsc(), b[perm])
+    x = to_np(prob.solve_interior(to_cuda(b)))
+    x32 = to_np(prob.solve_interior(to_cuda(b), precision=edd.F32))
+    e64 = np.linalg.norm(x[perm] - xr) / np.linalg.norm(xr)
+    e32 = np.linalg.norm(x32[perm] - xr) / np.linalg.norm(xr)
+    print(f"kd {prob.info['max_band']}, dissect {dissect}, variant {variant}: "
+          f"FP64 {e64:.2e}, FP32 factors {e32:.2e}")
+    assert e64 <= 1e-12 and e32 <= 1e-5
+    prob.close()
+
+
 def test_autotune_picks_valid_variants_and_caches():
     require_gpu()
     p = _wide()
