@@ -163,6 +163,8 @@ struct edd_problem {
   int *face_ptr_d = nullptr;    // [n_faces+1] start of each face in face_node
   int *face_node_d = nullptr;   // gamma indices, node-id order inside a face
   int *face_class_d = nullptr;  // class of each face
+  int *face_blk_d = nullptr;    // workgroup -> face (-1: none), see precond_setup
+  int n_face_blocks = 0;
   int64_t *class_off_d = nullptr;  // offset of each class inverse
   int *rest_d = nullptr;        // gamma indices of cross-point nodes
   double *face_inv_d = nullptr; // dense inverses of the unweighted face blocks

@@ -734,34 +734,38 @@ __global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ su
 }
 
 // x_S = b_S - W_a^T y_a,tail - W_b^T y_b,tail (y in x); 64 columns per block,
-// rows split over the sixteen wavefronts and summed in a fixed order.
+// rows split over the sixteen wavefronts, eight rows a batch per lane (eight
+// loads in flight), and summed in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_sep_rhs(const SubDesc *__restrict__ subs,
                                                   const SepDesc *__restrict__ seps,
                                                   const T *__restrict__ W,
                                                   const double *__restrict__ b,
                                                   double *__restrict__ x) {
-  constexpr int NWV = 16;
+  constexpr int NWV = 16, U = 8;
   const SepDesc sd = seps[blockIdx.y];
   const int ns = sd.ns;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
   __shared__ double part[NWV][64];
-  double acc0 = 0.0, acc1 = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (j < ns) {
     for (int h = 0; h < 2; ++h) {
       const SubDesc leaf = subs[h ? sd.b : sd.a];
       const double *y = x + leaf.dof_off + leaf.n - ns;
       const T *Wh = W + sd.w_off + (int64_t)h * ns * ns + j;
       int i = wv;
-      for (; i + NWV < ns; i += 2 * NWV) {
-        acc0 = fma((double)Wh[(int64_t)i * ns], y[i], acc0);
-        acc1 = fma((double)Wh[(int64_t)(i + NWV) * ns], y[i + NWV], acc1);
+      for (; i + (U - 1) * NWV < ns; i += U * NWV) {
+        double wv8[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) wv8[u] = (double)Wh[(int64_t)(i + u * NWV) * ns];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u & 3] = fma(wv8[u], y[i + u * NWV], acc[u & 3]);
       }
-      if (i < ns) acc0 = fma((double)Wh[(int64_t)i * ns], y[i], acc0);
+      for (; i < ns; i += NWV) acc[0] = fma((double)Wh[(int64_t)i * ns], y[i], acc[0]);
     }
   }
-  part[wv][lane] = acc0 + acc1;
+  part[wv][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
   if (wv == 0 && j < ns) {
     const SubDesc S = subs[sd.s];
@@ -772,7 +776,8 @@ __global__ __launch_bounds__(1024) void k_sep_rhs(const SubDesc *__restrict__ su
   }
 }
 
-// y_h,tail -= W_h x_S, one wavefront per tail row.
+// y_h,tail -= W_h x_S, one wavefront per two tail rows (four columns a
+// batch per lane: eight loads in flight).
 template <typename T>
 __global__ __launch_bounds__(256) void k_sep_update(const SubDesc *__restrict__ subs,
                                                     const SepDesc *__restrict__ seps,
@@ -781,17 +786,49 @@ __global__ __launch_bounds__(256) void k_sep_update(const SubDesc *__restrict__ 
   const SepDesc sd = seps[blockIdx.y >> 1];
   const int h = blockIdx.y & 1;
   const int ns = sd.ns;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i = 2 * (blockIdx.x * 4 + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (i >= ns) return;
+  const bool two = i + 1 < ns;
   const SubDesc leaf = subs[h ? sd.b : sd.a];
   const SubDesc S = subs[sd.s];
-  const T *row = W + sd.w_off + (int64_t)h * ns * ns + (int64_t)i * ns;
+  const T *r0 = W + sd.w_off + (int64_t)h * ns * ns + (int64_t)i * ns;
+  const T *r1 = two ? r0 + ns : r0;
   const double *xs = x + S.dof_off;
-  double acc = 0.0;
-  for (int j = lane; j < ns; j += 64) acc = fma((double)row[j], xs[j], acc);
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
-  if (lane == 0) x[leaf.dof_off + leaf.n - ns + i] -= acc;
+  double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
+  int j = lane;
+  for (; j + 192 < ns; j += 256) {
+    double w0[4], w1[4], xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      w0[u] = (double)r0[j + 64 * u];
+      w1[u] = (double)r1[j + 64 * u];
+      xv[u] = xs[j + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u & 1) {
+        a1 = fma(w0[u], xv[u], a1);
+        c1 = fma(w1[u], xv[u], c1);
+      } else {
+        a0 = fma(w0[u], xv[u], a0);
+        c0 = fma(w1[u], xv[u], c0);
+      }
+    }
+  }
+  for (; j < ns; j += 64) {
+    a0 = fma((double)r0[j], xs[j], a0);
+    c0 = fma((double)r1[j], xs[j], c0);
+  }
+  double a = a0 + a1, c = c0 + c1;
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off);
+    c += __shfl_down(c, off);
+  }
+  if (lane == 0) {
+    x[leaf.dof_off + leaf.n - ns + i] -= a;
+    if (two) x[leaf.dof_off + leaf.n - ns + i + 1] -= c;
+  }
 }
 
 __global__ void k_f64_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
@@ -894,7 +931,7 @@ static void solve_dissected(edd_problem *p, const T *C, const T *R, const T *W,
   k_sep_rhs<T><<<dim3((maxns + 63) / 64, p->n_sep), 1024, 0, p->stream>>>(p->subs_d, p->seps_d,
                                                                         W, b, x);
   solve_wide_launch<T, double, CW, DB>(p, C, R, x, x, p->order_sep_d, p->n_sep, 0);
-  k_sep_update<T><<<dim3((maxns + 3) / 4, 2 * p->n_sep), 256, 0, p->stream>>>(
+  k_sep_update<T><<<dim3((maxns + 7) / 8, 2 * p->n_sep), 256, 0, p->stream>>>(
       p->subs_d, p->seps_d, W, x);
   solve_wide_launch<T, double, CW, DB>(p, C, R, x, x, p->order_leaf_d, nleaf, 2);
 }

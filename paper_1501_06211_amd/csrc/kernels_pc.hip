@@ -117,6 +117,35 @@ __global__ __launch_bounds__(kBlock) void k_sk_diag(
 }
 
 // y = L x for D interleaved components
+// acc[c] += sum_k val[k] * x[col[k]*D + c] over one CSR row, in order of k,
+// four entries' loads issued together
+template <int D>
+__device__ inline void csr_row(int k0, int k1, const int *__restrict__ col,
+                               const double *__restrict__ val, const double *__restrict__ x,
+                               double (&acc)[D]) {
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    double v[4], xv[4][D];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v[u] = val[k + u];
+      const int64_t j = col[k + u];
+#pragma unroll
+      for (int c = 0; c < D; ++c) xv[u][c] = x[j * D + c];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] = fma(v[u], xv[u][c], acc[c]);
+  }
+  for (; k < k1; ++k) {
+    const double v = val[k];
+    const int64_t j = col[k];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = fma(v, x[j * D + c], acc[c]);
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nG, const int *__restrict__ rowptr,
                                                  const int *__restrict__ col,
@@ -128,14 +157,32 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nG, const int *__restri
   double acc[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) acc[c] = 0.0;
-  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-    const double v = val[k];
-    const int64_t j = col[k];
-#pragma unroll
-    for (int c = 0; c < D; ++c) acc[c] = fma(v, x[j * D + c], acc[c]);
-  }
+  csr_row<D>(rowptr[i], rowptr[i + 1], col, val, x, acc);
 #pragma unroll
   for (int c = 0; c < D; ++c) y[i * D + c] = acc[c];
+}
+
+// acc[c] += sum_{j0 <= j < j1} A[j*m + i] * rs[j*D + c], in order of j, with
+// eight loads of A in flight (the loads are independent; only the sums
+// chain).
+template <int D>
+__device__ inline void face_row_sum(const double *__restrict__ A, int m, int i, int j0, int j1,
+                                    const double *rs, double (&acc)[D]) {
+  int j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = A[(int64_t)(j + u) * m + i];  // symmetric
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] = fma(a[u], rs[(j + u) * D + c], acc[c]);
+  }
+  for (; j < j1; ++j) {
+    const double a = A[(int64_t)j * m + i];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = fma(a, rs[j * D + c], acc[c]);
+  }
 }
 
 // face blocks: z_f = S^{-1} A_class^{-1} S^{-1} r_f; one workgroup per face,
@@ -144,14 +191,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t nG, const int *__restri
 constexpr int kFaceQ = 4;
 
 template <int D>
-__global__ __launch_bounds__(256 * kFaceQ) void k_face_apply(
-    const int *__restrict__ fptr, const int *__restrict__ fnode,
+__global__ __launch_bounds__(256 * kFaceQ, 8) void k_face_apply(
+    const int *__restrict__ fblk, const int *__restrict__ fptr, const int *__restrict__ fnode,
     const int *__restrict__ fclass, const int64_t *__restrict__ coff,
     const double *__restrict__ inv, const double *__restrict__ S,
     const double *__restrict__ r, double *__restrict__ z) {
   __shared__ double rs[kMaxFace * D];
   __shared__ double part[kFaceQ][kMaxFace * D];
-  const int f = blockIdx.x;
+  const int f = fblk[blockIdx.x];
+  if (f < 0) return;  // an empty launch slot (whole workgroup)
   const int b0 = fptr[f], m = fptr[f + 1] - b0;
   const double *A = inv + coff[fclass[f]];
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
@@ -167,11 +215,7 @@ __global__ __launch_bounds__(256 * kFaceQ) void k_face_apply(
     double acc[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = 0.0;
-    for (int j = j0; j < j1; ++j) {
-      const double a = A[(int64_t)j * m + i];  // symmetric: column j, row i
-#pragma unroll
-      for (int c = 0; c < D; ++c) acc[c] = fma(a, rs[j * D + c], acc[c]);
-    }
+    face_row_sum<D>(A, m, i, j0, j1, rs, acc);
 #pragma unroll
     for (int c = 0; c < D; ++c) part[q][i * D + c] = acc[c];
   }
@@ -215,12 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t nG, const int *__re
     double acc[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = 0.0;
-    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-      const double v = val[k];
-      const int64_t j = col[k];
-#pragma unroll
-      for (int c = 0; c < D; ++c) acc[c] = fma(v, x[j * D + c], acc[c]);
-    }
+    csr_row<D>(rowptr[i], rowptr[i + 1], col, val, x, acc);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       y[i * D + c] = acc[c];
@@ -241,8 +280,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t nG, const int *__re
 // z = S^{-1} A^{-1} S^{-1} r on the face; INIT also writes pdir = z.  The
 // face's sum of r.z per component goes to partials[f*D + c].
 template <int D, bool INIT>
-__global__ __launch_bounds__(256 * kFaceQ) void k_face_pcg(
-    const int *__restrict__ fptr, const int *__restrict__ fnode,
+__global__ __launch_bounds__(256 * kFaceQ, 8) void k_face_pcg(
+    const int *__restrict__ fblk, const int *__restrict__ fptr, const int *__restrict__ fnode,
     const int *__restrict__ fclass, const int64_t *__restrict__ coff,
     const double *__restrict__ inv, const double *__restrict__ S,
     const double *__restrict__ scal, int rz, int pq, double *__restrict__ y,
@@ -252,7 +291,8 @@ __global__ __launch_bounds__(256 * kFaceQ) void k_face_pcg(
   __shared__ double rn[kMaxFace * D];
   __shared__ double part[kFaceQ][kMaxFace * D];
   __shared__ double red[kFaceQ * 4][D];
-  const int f = blockIdx.x;
+  const int f = fblk[blockIdx.x];
+  if (f < 0) return;  // an empty launch slot (whole workgroup)
   const int b0 = fptr[f], m = fptr[f + 1] - b0;
   const double *A = inv + coff[fclass[f]];
   double a[D];
@@ -283,11 +323,7 @@ __global__ __launch_bounds__(256 * kFaceQ) void k_face_pcg(
     double acc[D];
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = 0.0;
-    for (int j = j0; j < j1; ++j) {
-      const double av = A[(int64_t)j * m + i];  // symmetric: column j, row i
-#pragma unroll
-      for (int c = 0; c < D; ++c) acc[c] = fma(av, rs[j * D + c], acc[c]);
-    }
+    face_row_sum<D>(A, m, i, j0, j1, rs, acc);
 #pragma unroll
     for (int c = 0; c < D; ++c) part[qq0][i * D + c] = acc[c];
   }
@@ -912,6 +948,20 @@ int precond_setup(edd_problem *p) {
   }
   p->n_faces = (int)faces.size();
   p->n_face_classes = (int)class_inv.size();
+  // Workgroup b of a face launch runs on XCD b % kXcd (round-robin
+  // dispatch).  Faces sorted by class and cut into kXcd contiguous runs, one
+  // per XCD, keep each class's dense inverse in the L2 of one or two XCDs
+  // instead of streaming every class through every XCD.
+  constexpr int kXcd = 8;
+  std::vector<int> by_class(p->n_faces);
+  std::iota(by_class.begin(), by_class.end(), 0);
+  std::stable_sort(by_class.begin(), by_class.end(),
+                   [&](int a, int b) { return fclass[a] < fclass[b]; });
+  const int per_xcd = (p->n_faces + kXcd - 1) / kXcd;
+  std::vector<int> fblk((size_t)kXcd * per_xcd, -1);
+  for (int q = 0; q < p->n_faces; ++q)
+    fblk[(size_t)(q % per_xcd) * kXcd + q / per_xcd] = by_class[q];
+  p->n_face_blocks = (int)fblk.size();
   p->n_rest = (int)rest.size();
   p->face_inv_entries = (int64_t)inv_all.size();
 
@@ -942,6 +992,7 @@ int precond_setup(edd_problem *p) {
   PC_ALLOC(p->face_ptr_d, int, fptr.size());
   PC_ALLOC(p->face_node_d, int, fnode.size());
   PC_ALLOC(p->face_class_d, int, fclass.size());
+  PC_ALLOC(p->face_blk_d, int, fblk.size());
   PC_ALLOC(p->class_off_d, int64_t, coff.size());
   PC_ALLOC(p->rest_d, int, rest.size());
   PC_ALLOC(p->face_inv_d, double, inv_all.size());
@@ -957,6 +1008,7 @@ int precond_setup(edd_problem *p) {
             up(p->face_ptr_d, fptr.data(), sizeof(int) * fptr.size()) &&
             up(p->face_node_d, fnode.data(), sizeof(int) * fnode.size()) &&
             up(p->face_class_d, fclass.data(), sizeof(int) * fclass.size()) &&
+            up(p->face_blk_d, fblk.data(), sizeof(int) * fblk.size()) &&
             up(p->class_off_d, coff.data(), sizeof(int64_t) * coff.size()) &&
             up(p->rest_d, rest.data(), sizeof(int) * rest.size()) &&
             up(p->face_inv_d, inv_all.data(), sizeof(double) * inv_all.size());
@@ -1012,8 +1064,8 @@ struct PC {
 
   void face_precond(const double *r, double *z) {
     if (p->n_faces)
-      k_face_apply<D><<<p->n_faces, 256 * kFaceQ, 0, p->stream>>>(
-          p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d, p->face_inv_d,
+      k_face_apply<D><<<p->n_face_blocks, 256 * kFaceQ, 0, p->stream>>>(
+          p->face_blk_d, p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d, p->face_inv_d,
           p->skS_d, r, z);
     if (p->n_rest)
       k_rest_apply<D><<<(unsigned)((p->n_rest + kBlock - 1) / kBlock), kBlock, 0, p->stream>>>(
@@ -1034,8 +1086,8 @@ struct PC {
                 double *pdir, int out_slot) {
     const unsigned nrb = rest_blocks();
     if (p->n_faces)
-      k_face_pcg<D, INIT><<<p->n_faces, 256 * kFaceQ, 0, p->stream>>>(
-          p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d, p->face_inv_d,
+      k_face_pcg<D, INIT><<<p->n_face_blocks, 256 * kFaceQ, 0, p->stream>>>(
+          p->face_blk_d, p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d, p->face_inv_d,
           p->skS_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir, p->partials_d);
     if (p->n_rest)
       k_rest_pcg<D, INIT><<<nrb, kBlock, 0, p->stream>>>(
