@@ -188,7 +188,7 @@ __device__ inline void face_row_sum(const double *__restrict__ A, int m, int i, 
 // face blocks: z_f = S^{-1} A_class^{-1} S^{-1} r_f; one workgroup per face,
 // each row's sum split over four quarters of the columns (shorter dependent
 // load chains) and the quarters added in a fixed order.
-constexpr int kFaceQ = 4;
+constexpr int kFaceQ = 2;
 
 template <int D>
 __global__ __launch_bounds__(256 * kFaceQ, 8) void k_face_apply(
@@ -273,12 +273,54 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(int64_t nG, const int *__re
   }
 }
 
+// The rest nodes of the fused step below (diagonal preconditioner):
+// nodes t0, t0 + stride, ... of the rest list; the workgroup's sum of r.z
+// per component goes to out[c].
+template <int D, bool INIT>
+__device__ inline void rest_pcg_part(int64_t n, int64_t t0, int64_t stride,
+                                     const int *__restrict__ rest, const double *__restrict__ Ld,
+                                     const double *__restrict__ scal, int rz, int pq,
+                                     double *__restrict__ y, const double *__restrict__ p,
+                                     double *__restrict__ r, const double *__restrict__ q,
+                                     double *__restrict__ z, double *__restrict__ pdir,
+                                     double *__restrict__ out, double *red) {
+  double dot[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) dot[c] = 0.0;
+  for (int64_t t = t0; t < n; t += stride) {
+    const int64_t g = rest[t];
+    const double s = 1.0 / Ld[g];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double rv = r[g * D + c];
+      if (!INIT) {
+        const double den = scal[pq + c];
+        const double a = den != 0.0 ? scal[rz + c] / den : 0.0;
+        y[g * D + c] = fma(a, p[g * D + c], y[g * D + c]);
+        rv = fma(-a, q[g * D + c], rv);
+        r[g * D + c] = rv;
+      }
+      const double zv = rv * s;
+      z[g * D + c] = zv;
+      if (INIT) pdir[g * D + c] = zv;
+      dot[c] = fma(rv, zv, dot[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sm = block_sum(dot[c], red);
+    if (threadIdx.x == 0) out[c] = sm;
+  }
+}
+
 // The face-block preconditioner fused with the PCG update that precedes it
 // and the r.z partial sums that follow it.  Unless INIT: per component
 // a = scal[rz]/scal[pq], y += a p and r -= a q on the face's nodes (every
 // interface node is in exactly one face or in the rest set).  Then
 // z = S^{-1} A^{-1} S^{-1} r on the face; INIT also writes pdir = z.  The
-// face's sum of r.z per component goes to partials[f*D + c].
+// face's sum of r.z per component goes to partials[f*D + c].  Workgroups
+// past the nfb face slots treat the rest nodes (diagonal preconditioner),
+// their sums at partials[(n_faces + k)*D + c] for the k-th such workgroup.
 template <int D, bool INIT>
 __global__ __launch_bounds__(256 * kFaceQ, 8) void k_face_pcg(
     const int *__restrict__ fblk, const int *__restrict__ fptr, const int *__restrict__ fnode,
@@ -286,11 +328,20 @@ __global__ __launch_bounds__(256 * kFaceQ, 8) void k_face_pcg(
     const double *__restrict__ inv, const double *__restrict__ S,
     const double *__restrict__ scal, int rz, int pq, double *__restrict__ y,
     const double *__restrict__ p, double *__restrict__ r, const double *__restrict__ q,
-    double *__restrict__ z, double *__restrict__ pdir, double *__restrict__ partials) {
+    double *__restrict__ z, double *__restrict__ pdir, double *__restrict__ partials,
+    int nfb, int n_faces, int64_t n_rest, const int *__restrict__ rest,
+    const double *__restrict__ Ld) {
   __shared__ double rs[kMaxFace * D];
   __shared__ double rn[kMaxFace * D];
   __shared__ double part[kFaceQ][kMaxFace * D];
   __shared__ double red[kFaceQ * 4][D];
+  if ((int)blockIdx.x >= nfb) {  // the workgroups after the face slots: rest nodes
+    const int rb = blockIdx.x - nfb, nrb = gridDim.x - nfb;
+    rest_pcg_part<D, INIT>(n_rest, (int64_t)rb * blockDim.x + threadIdx.x,
+                           (int64_t)nrb * blockDim.x, rest, Ld, scal, rz, pq, y, p, r, q, z,
+                           pdir, partials + ((int64_t)n_faces + rb) * D, &red[0][0]);
+    return;
+  }
   const int f = fblk[blockIdx.x];
   if (f < 0) return;  // an empty launch slot (whole workgroup)
   const int b0 = fptr[f], m = fptr[f + 1] - b0;
@@ -358,46 +409,6 @@ __global__ __launch_bounds__(256 * kFaceQ, 8) void k_face_pcg(
     double sum = 0.0;
     for (int w2 = 0; w2 < kFaceQ * 4; ++w2) sum += red[w2][threadIdx.x];
     partials[(int64_t)f * D + threadIdx.x] = sum;
-  }
-}
-
-// The same for the nodes outside the faces (diagonal preconditioner);
-// partial sums at partials[(pbase + block)*D + c].
-template <int D, bool INIT>
-__global__ __launch_bounds__(kBlock) void k_rest_pcg(
-    int64_t n, const int *__restrict__ rest, const double *__restrict__ Ld,
-    const double *__restrict__ scal, int rz, int pq, double *__restrict__ y,
-    const double *__restrict__ p, double *__restrict__ r, const double *__restrict__ q,
-    double *__restrict__ z, double *__restrict__ pdir, double *__restrict__ partials,
-    int pbase) {
-  __shared__ double red[kBlock / 64];
-  double dot[D];
-#pragma unroll
-  for (int c = 0; c < D; ++c) dot[c] = 0.0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = rest[t];
-    const double s = 1.0 / Ld[g];
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      double rv = r[g * D + c];
-      if (!INIT) {
-        const double den = scal[pq + c];
-        const double a = den != 0.0 ? scal[rz + c] / den : 0.0;
-        y[g * D + c] = fma(a, p[g * D + c], y[g * D + c]);
-        rv = fma(-a, q[g * D + c], rv);
-        r[g * D + c] = rv;
-      }
-      const double zv = rv * s;
-      z[g * D + c] = zv;
-      if (INIT) pdir[g * D + c] = zv;
-      dot[c] = fma(rv, zv, dot[c]);
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    const double sm = block_sum(dot[c], red);
-    if (threadIdx.x == 0) partials[(pbase + (int64_t)blockIdx.x) * D + c] = sm;
   }
 }
 
@@ -1085,14 +1096,11 @@ struct PC {
   void face_pcg(int rz, double *y, const double *pv, double *r, const double *q, double *z,
                 double *pdir, int out_slot) {
     const unsigned nrb = rest_blocks();
-    if (p->n_faces)
-      k_face_pcg<D, INIT><<<p->n_face_blocks, 256 * kFaceQ, 0, p->stream>>>(
-          p->face_blk_d, p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d, p->face_inv_d,
-          p->skS_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir, p->partials_d);
-    if (p->n_rest)
-      k_rest_pcg<D, INIT><<<nrb, kBlock, 0, p->stream>>>(
-          p->n_rest, p->rest_d, p->skLdiag_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir,
-          p->partials_d, p->n_faces);
+    const int nfb = p->n_faces ? p->n_face_blocks : 0;
+    k_face_pcg<D, INIT><<<nfb + nrb, 256 * kFaceQ, 0, p->stream>>>(
+        p->face_blk_d, p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d,
+        p->face_inv_d, p->skS_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir, p->partials_d, nfb,
+        p->n_faces, p->n_rest, p->rest_d, p->skLdiag_d);
     if (out_slot >= 0)
       k_reduce<<<D, kBlock, 0, p->stream>>>(p->partials_d, (int)(p->n_faces + (p->n_rest ? nrb : 0)),
                                             D, p->scal_d + out_slot);
@@ -1101,7 +1109,7 @@ struct PC {
   // grids of the fused kernels (grid-stride loops, so capped); the fused
   // path needs one partial sum per block and component
   unsigned rest_blocks() const {
-    return (unsigned)std::min<int64_t>((p->n_rest + kBlock - 1) / kBlock, 1024);
+    return (unsigned)std::min<int64_t>((p->n_rest + 256 * kFaceQ - 1) / (256 * kFaceQ), 1024);
   }
   unsigned spmv_blocks() const { return std::min(g1, 4096u); }
   bool fused_fits() const {
