@@ -119,9 +119,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// partials[b*m + j] = sum over the block's range of z[i] * W[j*n + i]
-// partials[b*m + j] = <z, W_j> over block b's chunk; eight vectors share
-// each reduction (wavefront shuffles, one barrier), summed in a fixed order.
+// partials[b*m + j] = <z, W_j> over row chunk b = blockIdx.x, for the eight
+// vectors j of group blockIdx.y (one workgroup per chunk and group, so the
+// window's vectors stream in parallel); the eight share each reduction
+// (wavefront shuffles, one barrier), summed in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_window_dots(
     int64_t n, int m, const double *__restrict__ W, const double *__restrict__ z,
     double *__restrict__ partials) {
@@ -131,7 +132,9 @@ __global__ __launch_bounds__(kBlock) void k_window_dots(
   const int64_t lo = blockIdx.x * chunk;
   const int64_t hi = min(n, lo + chunk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int j0 = 0; j0 < m; j0 += JB) {
+  // blockIdx.y picks a group of JB vectors; blockIdx.x the chunk of rows
+  {
+    const int j0 = blockIdx.y * JB;
     const int nj = min(JB, m - j0);
     double acc[JB];
 #pragma unroll
@@ -156,7 +159,6 @@ __global__ __launch_bounds__(kBlock) void k_window_dots(
       for (int w = 0; w < NW; ++w) s += red[threadIdx.x][w];
       partials[(int64_t)blockIdx.x * m + j0 + threadIdx.x] = s;
     }
-    __syncthreads();
   }
 }
 
@@ -171,7 +173,15 @@ __global__ __launch_bounds__(kBlock) void k_window_combine(
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     double v = z[i];
-    for (int j = 0; j < m; ++j) v = fma(-coef[j], P[(int64_t)j * n + i], v);
+    int j = 0;
+    for (; j + 4 <= m; j += 4) {  // four loads in flight, same order of terms
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = P[(int64_t)(j + u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v = fma(-coef[j + u], a[u], v);
+    }
+    for (; j < m; ++j) v = fma(-coef[j], P[(int64_t)j * n + i], v);
     pv[i] = v;
   }
 }
@@ -257,7 +267,7 @@ void launch_window_dots(edd_problem *p, int64_t n, int m, const double *W,
   if (m <= 0) return;
   unsigned g = grid_for(n);
   if (g > 256) g = 256;
-  k_window_dots<<<g, kBlock, 0, p->stream>>>(n, m, W, z, p->partials_d);
+  k_window_dots<<<dim3(g, (m + 7) / 8), kBlock, 0, p->stream>>>(n, m, W, z, p->partials_d);
   k_reduce<<<m, kBlock, 0, p->stream>>>(p->partials_d, (int)g, m, p->scal_d + slot);
 }
 
