@@ -263,7 +263,8 @@ int edd_solve_batch(edd_problem *const *ps, int n, const double *const *f_dev,
  * 4-6: wide bands, a dedicated chain wavefront and 1024 threads, two load
  * chunk widths, the narrower one also double-buffered) on the current factors, for FP64 and (if present) FP32
  * factors, and keeps the fastest.  Results are cached per shape class
- * (device, dimension, subdomain count, band extents) for the process;
+ * (device, dimension, subdomain count, band extents, factor precisions) for
+ * the process;
  * force != 0 re-times.  variants (2 ints, FP64 then FP32) may be NULL.
  * Needs edd_set_element_moduli.  Synchronises. */
 int edd_autotune(edd_problem *p, int force, int *variants);

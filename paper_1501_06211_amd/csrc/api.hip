@@ -866,7 +866,8 @@ int edd_autotune(edd_problem *p, int force, int *variants) {
   // shape class: device, dimension, subdomain count and band extents
   const std::string key = std::string(prop.gcnArchName) + "|" + std::to_string(p->g.dim) + "|" +
                           std::to_string(p->n_blk) + "|" + std::to_string(p->max_kd) + "|" +
-                          std::to_string(p->max_np) + "|" + std::to_string(p->fac_entries);
+                          std::to_string(p->max_np) + "|" + std::to_string(p->fac_entries) +
+                          "|" + std::to_string(p->factor_precision);
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
