@@ -102,9 +102,14 @@ def test_wide_variants_at_half_bandwidths_past_448(variant, dissect):
 
 def test_autotune_picks_valid_variants_and_caches():
     require_gpu()
+    from paper_1501_06211_amd import edd
     p = _wide()
+    p64 = make_problem(p, factor_precision=edd.F64)
+    v64 = p64.autotune(force=True)
+    assert 1 <= v64[0] <= 6 and v64[1] == 0  # no FP32 factors: nothing to tune
+    p64.close()
     prob = make_problem(p)
-    v = prob.autotune(force=True)
+    v = prob.autotune()  # factor precisions are part of the cache key
     assert all(1 <= x <= 6 for x in v)
     prob2 = make_problem(p)
     assert prob2.autotune() == v  # same shape class: cached
