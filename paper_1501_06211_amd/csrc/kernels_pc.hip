@@ -186,8 +186,8 @@ __device__ inline void face_row_sum(const double *__restrict__ A, int m, int i, 
 }
 
 // face blocks: z_f = S^{-1} A_class^{-1} S^{-1} r_f; one workgroup per face,
-// each row's sum split over four quarters of the columns (shorter dependent
-// load chains) and the quarters added in a fixed order.
+// each row's sum split over kFaceQ parts of the columns (shorter dependent
+// load chains), 256 threads per part, the parts added in a fixed order.
 constexpr int kFaceQ = 2;
 
 template <int D>
