@@ -160,9 +160,7 @@ __global__ __launch_bounds__(256) void k_apply_tiled(
   constexpr int ND = D * NC;
   __shared__ double us[HX * HY * HZ * D];
   __shared__ double Es[EX * EY * EZ];
-  __shared__ double K0s[ND * ND];
   const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY, k0 = blockIdx.z * TZ;
-  for (int q = threadIdx.x; q < ND * ND; q += 256) K0s[q] = K0[q];
 #pragma unroll 1
   for (int q = threadIdx.x; q < HX * HY * HZ; q += 256) {
     const int hx = q % HX, hy = (q / HX) % HY, hz = q / (HX * HY);
@@ -218,7 +216,8 @@ __global__ __launch_bounds__(256) void k_apply_tiled(
         }
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-          const double *row = K0s + (a * D + c) * ND;
+          // wave-uniform row: read through the scalar cache into SGPRs
+          const double *row = K0 + (a * D + c) * ND;
           double acc = 0.0;
 #pragma unroll
           for (int m = 0; m < ND; ++m) acc = fma(row[m], xe[m], acc);
