@@ -357,20 +357,20 @@ def main():
     args = parse()
     if args.workload == "sequence":
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+            print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                               "n_gpus": args.gpus}))
             sys.exit(2)
         run_sequence(args)
         return
     if args.workload == "batch":
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+            print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                               "n_gpus": args.gpus}))
             sys.exit(2)
         run_batch(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
