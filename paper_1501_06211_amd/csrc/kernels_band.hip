@@ -193,46 +193,52 @@ __global__ __launch_bounds__(NT) void k_band_cholesky(
 // Solve layouts from the factor L (column band, true diagonal):
 //   Cs[p*ld + r] = L[p+r, p] with the diagonal replaced by 1/L[p,p]
 //   Rs[q*ld + k] = L[q, q-k]  with the diagonal replaced by 1/L[q,q]
-// Cs may alias L.  One block per (subdomain, tile of 64 rows q).
+// Cs may alias L (then only its diagonals change).  Work comes in 64x64
+// tiles (rows q or p, offsets k or r) per subdomain; a row-layout tile's
+// sources (q-k, k) lie on a skewed band of the column layout and are read
+// along k (contiguous within a column) into LDS, then written along k.
+// The only in-place change, the diagonal of column p, is read solely by
+// the row-layout tile of the same rows at offsets [0, 64), which writes it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_solve_layouts(
     const SubDesc *__restrict__ subs, const double *__restrict__ Lf,
     T *__restrict__ Cs, T *__restrict__ Rs) {
+  __shared__ double tile[64][65];
   const SubDesc s = subs[blockIdx.y];
   const int n = s.np, kd = s.kd, ld = kd + 1;
   const double *Lb = Lf + s.fac_off;
   T *Cb = Cs + s.fac_off;
   T *Rb = Rs + s.fac_off;
-  for (int q0 = blockIdx.x * 64; q0 < n; q0 += gridDim.x * 64) {
-    // rows q in [q0, q0+64): Rs[q*ld + k] = L[q - k][k] (column q-k, offset k)
-    for (int e = threadIdx.x; e < 64 * ld; e += blockDim.x) {
-      const int qq = e / ld, k = e - qq * ld, q = q0 + qq;
-      if (q >= n) continue;
-      const int p = q - k;
-      double v = 0.0;
-      if (p >= 0) v = Lb[(int64_t)p * ld + k];
-      if (k == 0) v = 1.0 / v;
-      Rb[(int64_t)q * ld + k] = (T)v;
-    }
-  }
-  __syncthreads();
   const bool inplace = (const void *)Cs == (const void *)Lf;
-  for (int q0 = blockIdx.x * 64; q0 < n; q0 += gridDim.x * 64) {
-    if (inplace) {
-      // only the diagonal changes
-      for (int qq = threadIdx.x; qq < 64; qq += blockDim.x) {
-        const int p = q0 + qq;
-        if (p < n) Cb[(int64_t)p * ld] = (T)(1.0 / Lb[(int64_t)p * ld]);
+  const int nqt = n / 64, nkt = (ld + 63) / 64;
+  for (int t = blockIdx.x; t < nqt * nkt; t += gridDim.x) {
+    const int q0 = (t / nkt) * 64, k0 = (t % nkt) * 64;
+    const int pmin = q0 - k0 - 63;  // sources p = q - k of this tile
+    for (int e = threadIdx.x; e < 127 * 64; e += blockDim.x) {
+      const int kk = e & 63, p = pmin + (e >> 6), k = k0 + kk, qq = p + k - q0;
+      if (qq < 0 || qq >= 64 || k >= ld) continue;
+      double v = p >= 0 ? Lb[(int64_t)p * ld + k] : 0.0;
+      if (k == 0) v = 1.0 / v;
+      tile[qq][kk] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+      const int qq = e >> 6, k = k0 + (e & 63);
+      if (k < ld) Rb[(int64_t)(q0 + qq) * ld + k] = (T)tile[qq][e & 63];
+    }
+    if (!inplace) {
+      for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        const int pp = e >> 6, r = k0 + (e & 63);
+        if (r >= ld) continue;
+        double v = Lb[(int64_t)(q0 + pp) * ld + r];
+        if (r == 0) v = 1.0 / v;
+        Cb[(int64_t)(q0 + pp) * ld + r] = (T)v;
       }
-      continue;
+    } else if (k0 == 0) {
+      for (int pp = threadIdx.x; pp < 64; pp += blockDim.x)
+        Cb[(int64_t)(q0 + pp) * ld] = (T)(1.0 / Lb[(int64_t)(q0 + pp) * ld]);
     }
-    for (int e = threadIdx.x; e < 64 * ld; e += blockDim.x) {
-      const int qq = e / ld, r = e - qq * ld, p = q0 + qq;
-      if (p >= n) continue;
-      double v = Lb[(int64_t)p * ld + r];
-      if (r == 0) v = 1.0 / v;
-      Cb[(int64_t)p * ld + r] = (T)v;
-    }
+    __syncthreads();  // the tile is reused by the next iteration
   }
 }
 
