@@ -412,6 +412,87 @@ __global__ __launch_bounds__(256 * kFaceQ, 8) void k_face_pcg(
   }
 }
 
+// The same step for faces of at most 64 nodes (2D edges): one wavefront
+// per face, four faces per workgroup, lane i owning row i; the face's r.z
+// sums go to partials[f*D + c].  Workgroups from nsb on treat the rest
+// nodes, as above.
+template <int D, bool INIT>
+__global__ __launch_bounds__(256) void k_face_pcg_small(
+    const int *__restrict__ fptr, const int *__restrict__ fnode,
+    const int *__restrict__ fclass, const int64_t *__restrict__ coff,
+    const double *__restrict__ inv, const double *__restrict__ S,
+    const double *__restrict__ scal, int rz, int pq, double *__restrict__ y,
+    const double *__restrict__ p, double *__restrict__ r, const double *__restrict__ q,
+    double *__restrict__ z, double *__restrict__ pdir, double *__restrict__ partials,
+    int n_faces, int nsb, int64_t n_rest, const int *__restrict__ rest,
+    const double *__restrict__ Ld) {
+  __shared__ double rs[4][64 * D];
+  __shared__ double red[4 * D];
+  if ((int)blockIdx.x >= nsb) {  // rest nodes
+    const int rb = blockIdx.x - nsb, nrb = gridDim.x - nsb;
+    rest_pcg_part<D, INIT>(n_rest, (int64_t)rb * blockDim.x + threadIdx.x,
+                           (int64_t)nrb * blockDim.x, rest, Ld, scal, rz, pq, y, p, r, q, z,
+                           pdir, partials + ((int64_t)n_faces + rb) * D, red);
+    return;
+  }
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int f = blockIdx.x * 4 + wv;
+  int b0 = 0, m = 0;
+  const double *A = inv;
+  if (f < n_faces) {
+    b0 = fptr[f];
+    m = fptr[f + 1] - b0;
+    A = inv + coff[fclass[f]];
+  }
+  double a[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double den = INIT ? 0.0 : scal[pq + c];
+    a[c] = (!INIT && den != 0.0) ? scal[rz + c] / den : 0.0;
+  }
+  int64_t g = 0;
+  double s = 0.0, rn[D];
+  if (lane < m) {
+    g = fnode[b0 + lane];
+    s = 1.0 / S[g];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double rv = r[g * D + c];
+      if (!INIT) {
+        y[g * D + c] = fma(a[c], p[g * D + c], y[g * D + c]);
+        rv = fma(-a[c], q[g * D + c], rv);
+        r[g * D + c] = rv;
+      }
+      rn[c] = rv;
+      rs[wv][lane * D + c] = rv * s;
+    }
+  }
+  __syncthreads();
+  double dot[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) dot[c] = 0.0;
+  if (lane < m) {
+    double acc[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = 0.0;
+    face_row_sum<D>(A, m, lane, 0, m, rs[wv], acc);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double zv = acc[c] * s;
+      z[g * D + c] = zv;
+      if (INIT) pdir[g * D + c] = zv;
+      dot[c] = rn[c] * zv;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    double v = dot[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0 && f < n_faces) partials[(int64_t)f * D + c] = v;
+  }
+}
+
 // p = z + (scal[rz_new]/scal[rz_old]) p per component.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_pcg_dir2(int64_t nG, const double *__restrict__ scal,
@@ -1096,11 +1177,19 @@ struct PC {
   void face_pcg(int rz, double *y, const double *pv, double *r, const double *q, double *z,
                 double *pdir, int out_slot) {
     const unsigned nrb = rest_blocks();
-    const int nfb = p->n_faces ? p->n_face_blocks : 0;
-    k_face_pcg<D, INIT><<<nfb + nrb, 256 * kFaceQ, 0, p->stream>>>(
-        p->face_blk_d, p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d,
-        p->face_inv_d, p->skS_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir, p->partials_d, nfb,
-        p->n_faces, p->n_rest, p->rest_d, p->skLdiag_d);
+    if (small_faces()) {
+      const int nsb = (p->n_faces + 3) / 4;
+      k_face_pcg_small<D, INIT><<<nsb + nrb, 256, 0, p->stream>>>(
+          p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d, p->face_inv_d,
+          p->skS_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir, p->partials_d, p->n_faces, nsb,
+          p->n_rest, p->rest_d, p->skLdiag_d);
+    } else {
+      const int nfb = p->n_faces ? p->n_face_blocks : 0;
+      k_face_pcg<D, INIT><<<nfb + nrb, 256 * kFaceQ, 0, p->stream>>>(
+          p->face_blk_d, p->face_ptr_d, p->face_node_d, p->face_class_d, p->class_off_d,
+          p->face_inv_d, p->skS_d, p->scal_d, rz, P_PQ, y, pv, r, q, z, pdir, p->partials_d,
+          nfb, p->n_faces, p->n_rest, p->rest_d, p->skLdiag_d);
+    }
     if (out_slot >= 0)
       k_reduce<<<D, kBlock, 0, p->stream>>>(p->partials_d, (int)(p->n_faces + (p->n_rest ? nrb : 0)),
                                             D, p->scal_d + out_slot);
@@ -1108,8 +1197,11 @@ struct PC {
 
   // grids of the fused kernels (grid-stride loops, so capped); the fused
   // path needs one partial sum per block and component
+  // faces of at most 64 nodes take the one-wavefront-per-face kernel
+  bool small_faces() const { return p->max_face_m <= 64; }
   unsigned rest_blocks() const {
-    return (unsigned)std::min<int64_t>((p->n_rest + 256 * kFaceQ - 1) / (256 * kFaceQ), 1024);
+    const int nt = small_faces() ? 256 : 256 * kFaceQ;
+    return (unsigned)std::min<int64_t>((p->n_rest + nt - 1) / nt, 1024);
   }
   unsigned spmv_blocks() const { return std::min(g1, 4096u); }
   bool fused_fits() const {
