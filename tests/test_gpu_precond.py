@@ -125,21 +125,23 @@ def test_skeleton_operators_parity(dim, weighted):
     prob.close()
 
 
-def test_device_resident_mode_matches_oracle_fixed_k():
+@pytest.mark.parametrize("dim", [2, 3])
+def test_device_resident_mode_matches_oracle_fixed_k(dim):
     """Fixed Lanczos steps and inner iterations, no host synchronisation:
     with enough inner iterations it reproduces the oracle's k-step inverse
-    Lanczos with exact Laplacian solves."""
+    Lanczos with exact Laplacian solves (2D: the one-wavefront-per-face
+    kernel for short faces; 3D: the column-split face kernel)."""
     require_gpu()
     from paper_1501_06211_amd import edd
-    p = _small3d()
+    p = _small2d() if dim == 2 else _small3d()
     prob = make_problem(p)
     M, L, g = iface.skeleton_matrices(p, lumped=True, weighted=True)
     rng = np.random.default_rng(3)
-    r = rng.standard_normal(len(g) * 3)
-    R = r.reshape(-1, 3)
+    r = rng.standard_normal(len(g) * dim)
+    R = r.reshape(-1, dim)
     for k in (4, 8):
         zref = np.column_stack([iface.inverse_lanczos(M, L, 0.5, R[:, c], kmax=k, tol=0.0)[0]
-                                for c in range(3)]).reshape(-1)
+                                for c in range(dim)]).reshape(-1)
         z = to_np(prob.apply_precond(to_cuda(r), precond=edd.PC_HTHETA, theta=0.5,
                                      lanczos_kmax=k, lanczos_tol=0.0, inner_tol=0.0,
                                      inner_maxit=300, interface_weighting=1))
