@@ -190,6 +190,242 @@ __global__ __launch_bounds__(NT) void k_band_cholesky(
   if (tid == 0) info[order[blockIdx.x]] = anybad;
 }
 
+// Band Cholesky for wide windows (more than 512 rows), same panels as
+// k_band_cholesky but with the update
+//   S[w, c] = -sum_{k < j0} L[j0+w, k] L[j0+c, k]
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l supplies
+// A(l%16, l/16) and B(l/16, l%16) and holds C rows l/16 + 4e, column l%16).
+// Wavefront v owns window rows 64v..64v+63 as 4 x 2 tiles of 16 x 16, so a
+// U value read from LDS serves 16 rows instead of one; the A operand streams
+// from the band exactly as before.  Tiles whose 16 rows all lie left of the
+// band for a k-step are skipped.  After the update the tiles pass through
+// LDS, 16 columns at a time, into one row per thread (the transpose buffer
+// reuses the U staging area), and the diagonal block and the row solves
+// proceed as in k_band_cholesky.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kMxNB = 32, kMxKC = 64, kTransLd = 17;
+
+constexpr int kDlLd = kMxNB + 2;  // 16-byte aligned rows
+constexpr int kMxHead = kMxNB * kDlLd + kMxNB + 64 + 2;  // Dl, Dinv, column, flag
+
+constexpr size_t chol_mfma_lds_bytes(int nt) {
+  // the small arrays first, so that their reads take immediate offsets,
+  // then the transpose area (which also holds the two U buffers)
+  return sizeof(double) * ((size_t)kMxHead + (size_t)nt * kTransLd);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_band_cholesky_mfma(
+    const SubDesc *__restrict__ subs, const int *__restrict__ order,
+    double *__restrict__ fac, int *__restrict__ info) {
+  constexpr int NB = kMxNB, KC = kMxKC, NW = NT / 64;
+  constexpr int UPT = KC * NB / NT;  // staged U values per thread
+  static_assert(NT % 64 == 0 && UPT * NT == KC * NB && NT * kTransLd >= 2 * KC * NB,
+                "two U buffers fit the transpose area");
+  extern __shared__ __attribute__((aligned(16))) double lds[];
+  // DlT[c][r] = L_D[r][c] (rows 16-byte aligned: pairs read as one 16-byte load)
+  double (*DlT)[kDlLd] = reinterpret_cast<double (*)[kDlLd]>(lds);
+  double *Dinv = lds + NB * kDlLd;
+  double *col = Dinv + NB;  // one column of the diagonal block, 64 rows
+  int *anybad = reinterpret_cast<int *>(col + 64);
+  double *T = lds + kMxHead;  // NT x kTransLd; the two U buffers alias its start
+  double *Ubuf = T;
+  const SubDesc s = subs[order[blockIdx.x]];
+  const int n = s.np, kd = s.kd, ld = kd + 1;  // n is a multiple of NB
+  double *L = fac + s.fac_off;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar branches
+  const int li = lane & 15, lk = lane >> 4;
+  const int w0 = wave * 64;  // first window row of this wavefront
+  if (tid == 0) *anybad = 0;
+
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int W = min(NB + kd, n - j0);
+    const int kt = j0 + w0 - kd;  // first column reaching row w0
+    // S starts as the panel of A: tile (rt, ct) slot e holds window row
+    // w0 + 16rt + lk + 4e, panel column 16ct + li, at L[j0*ld + w + c*kd]
+    v4d S[4][2];
+    if (w0 < W) {  // wave-uniform
+      const double *pA = L + (int64_t)j0 * ld + (w0 + lk) + (int64_t)li * kd;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int w = w0 + 16 * rt + lk + 4 * e, c = 16 * ct + li;
+            const double v = pA[16 * rt + 4 * e + (int64_t)16 * ct * kd];
+            S[rt][ct][e] = (w < W && c <= w && w - c <= kd) ? v : 0.0;
+          }
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) S[rt][ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    const int kbeg = max(0, j0 - kd);
+    // U chunks alternate between two buffers; the next chunk's values are
+    // loaded into registers before the current chunk's products and stored
+    // after them, one barrier per chunk
+    double un[UPT];
+    auto load_u = [&](int kc) {
+      const int kn = min(KC, j0 - kc);
+#pragma unroll
+      for (int q = 0; q < UPT; ++q) {
+        const int e = tid + q * NT, kk = e / NB, c = e - kk * NB, k = kc + kk;
+        const double v = L[(int64_t)k * ld + (j0 + c - k)];
+        un[q] = (kk < kn && j0 + c - k <= kd) ? v : 0.0;
+      }
+    };
+    auto store_u = [&](double *Ub) {
+#pragma unroll
+      for (int q = 0; q < UPT; ++q) Ub[tid + q * NT] = un[q];
+    };
+    __syncthreads();  // the previous panel's columns are written back
+    if (kbeg < j0) {
+      load_u(kbeg);
+      store_u(Ubuf);
+    }
+    int par = 0;
+    for (int kc = kbeg; kc < j0; kc += KC, par ^= 1) {
+      const int kn = min(KC, j0 - kc);
+      __syncthreads();  // chunk kc visible; the other buffer's readers are done
+      const bool more = kc + KC < j0;
+      if (more) load_u(kc + KC);
+      const double(*U)[NB] = reinterpret_cast<const double(*)[NB]>(Ubuf + par * KC * NB);
+      // batches of 8 columns from the first that reaches row w0
+      const int ks0 = kt - kc >= 8 ? ((kt - kc) & ~7) : 0;
+      if (w0 < W && kc + kn > kt && ks0 < kn) {  // wave-uniform
+        // (j0+w, k) sits at L[k*ld + j0+w-k] = L[k*kd + j0+w]: one lane
+        // pointer, +16 per row tile and +4*kd per k-step
+        const double *pa = L + (int64_t)(kc + lk) * kd + (j0 + w0 + li);
+        const int lead = kc + lk + kd - j0 - w0 - li;  // row offset of the band edge
+        double an[2][4];
+        auto load_a = [&](int ks) {
+          const double *pk = pa + ks * kd;
+#pragma unroll
+          for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) an[st][rt] = pk[st * 4 * kd + 16 * rt];
+        };
+        load_a(ks0);
+        for (int ks = ks0; ks < kn; ks += 8) {
+          double a[2][4], b[2][2];
+#pragma unroll
+          for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) a[st][rt] = an[st][rt];
+          if (ks + 8 < kn) load_a(ks + 8);  // in flight during this batch
+#pragma unroll
+          for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) b[st][ct] = U[ks + 4 * st + lk][16 * ct + li];
+#pragma unroll
+          for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+              // kept: k < j0 (inside this chunk), j0+w-k <= kd, w < W
+              const bool in = ks + 4 * st + lk < kn && lead + ks + 4 * st >= 16 * rt &&
+                              w0 + 16 * rt + li < W;
+              a[st][rt] = in ? -a[st][rt] : 0.0;
+            }
+#pragma unroll
+          for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+              if (kc + ks + 4 * st + 4 <= kt + 16 * rt) continue;  // tile left of the band
+#pragma unroll
+              for (int ct = 0; ct < 2; ++ct)
+                S[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][rt], b[st][ct],
+                                                                  S[rt][ct], 0, 0, 0);
+            }
+        }
+      }
+      if (more) store_u(Ubuf + (par ^ 1) * KC * NB);
+    }
+    // tiles -> one window row per thread (16 columns at a time)
+    double acc[NB];
+    double *Tw = T + w0 * kTransLd;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      __syncthreads();  // U (first half) or the previous half is consumed
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Tw[(16 * rt + lk + 4 * e) * kTransLd + li] = S[rt][ct][e];
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc[16 * ct + c] = Tw[lane * kTransLd + c];
+    }
+    const int w = tid;
+    // Diagonal block by wavefront 0 (rows 0..63 of the window, right-looking
+    // as in k_band_cholesky).  Each scaled column goes through LDS and is
+    // read back as broadcasts; 1/sqrt of the pivot is the hardware estimate
+    // refined by two Newton steps, y <- y + y (1 - p y^2) / 2 (each squares
+    // the relative error).
+    if (tid < 64) {
+      bool bad = false;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double piv = lane_bcast(acc[c], c);
+        bad = bad || !(piv > 0.0);
+        const double pv = piv > 0.0 ? piv : 1.0;
+        double y = __builtin_amdgcn_rsq(pv);
+#pragma unroll
+        for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-pv * y, y, 1.0), y);
+        const double rd = y, dc = pv * y;
+        acc[c] = (w == c) ? dc : acc[c] * rd;
+        if (w == 0) Dinv[c] = rd;
+        if (w < NB) DlT[c][w] = acc[c];
+        if (c + 1 < NB) {
+          col[w] = acc[c];
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          const double2 *col2 = reinterpret_cast<const double2 *>(col);
+#pragma unroll
+          for (int q = (c + 1) / 2; q < NB / 2; ++q) {
+            const double2 v = col2[q];
+            if (2 * q > c) acc[2 * q] = fma(-acc[c], v.x, acc[2 * q]);
+            acc[2 * q + 1] = fma(-acc[c], v.y, acc[2 * q + 1]);
+            // keep the update here (not sunk to the column's pivot, which
+            // would hold every broadcast value live across the loop)
+            asm volatile("" : "+v"(acc[2 * q]), "+v"(acc[2 * q + 1]));
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();  // all reads done before the next column is stored
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+      if (bad && w == 0) *anybad = 1;
+    }
+    __syncthreads();
+    // rows below: solve x L_D^T = a, right-looking over the columns of L_D
+    if (w < W && w >= 64) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        acc[c] *= Dinv[c];
+        const double2 *d2 = reinterpret_cast<const double2 *>(DlT[c]);
+#pragma unroll
+        for (int q = (c + 1) / 2; q < NB / 2; ++q) {
+          const double2 v = d2[q];
+          if (2 * q > c) acc[2 * q] = fma(-acc[c], v.x, acc[2 * q]);
+          acc[2 * q + 1] = fma(-acc[c], v.y, acc[2 * q + 1]);
+          if (q % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    if (w < W) {
+      double *rowp = L + (int64_t)j0 * ld + w;
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c <= w && w - c <= kd) rowp[c * kd] = acc[c];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) info[order[blockIdx.x]] = *anybad;
+}
+
 // Solve layouts from the factor L (column band, true diagonal):
 //   Cs[p*ld + r] = L[p+r, p] with the diagonal replaced by 1/L[p,p]
 //   Rs[q*ld + k] = L[q, q-k]  with the diagonal replaced by 1/L[q,q]
@@ -849,6 +1085,14 @@ void chol_launch(edd_problem *p, const int *order, int count) {
       p->subs_d, order, p->fac64_d, p->info_d);
 }
 
+template <int NT>
+void chol_launch_mfma(edd_problem *p, const int *order, int count) {
+  if (count <= 0) return;
+  set_lds_limit_once((const void *)k_band_cholesky_mfma<NT>, p);
+  k_band_cholesky_mfma<NT><<<count, NT, chol_mfma_lds_bytes(NT), p->stream>>>(
+      p->subs_d, order, p->fac64_d, p->info_d);
+}
+
 template <typename T, typename W, int NT>
 void solve_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x) {
   const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
@@ -875,7 +1119,9 @@ static void cholesky_subset(edd_problem *p, const int *order, int count) {
   else if (rows <= 128) chol_launch<128, 1>(p, order, count);
   else if (rows <= 256) chol_launch<128, 2>(p, order, count);
   else if (rows <= 512) chol_launch<256, 2>(p, order, count);
-  else chol_launch<1024, 1>(p, order, count);  // kd <= 992 (checked at setup)
+  else if (chol_mfma_lds_bytes(1024) <= p->lds_limit)
+    chol_launch_mfma<1024>(p, order, count);  // kd <= 992 (checked at setup)
+  else chol_launch<1024, 1>(p, order, count);
 }
 
 // Factor every band block; for dissected interiors the halves first, then
