@@ -241,9 +241,11 @@ void launch_check_moduli(edd_problem *p, const double *E, double *flag);
 void launch_convert_moduli(edd_problem *p, const void *E, int dtype);
 void launch_mask_dirichlet(edd_problem *p, double *v);
 
-// kernels_band.hip
+// kernels_factor.hip
 void launch_band_cholesky(edd_problem *p);
 void launch_band_layouts(edd_problem *p);
+
+// kernels_band.hip
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x);
 bool band_solve_variant_ok(const edd_problem *p, int v);
@@ -269,9 +271,29 @@ void launch_cg_update(edd_problem *p, int64_t n, int num, int den,
                       const double *q, int slot, int copy_dst, int flag_slot);
 void launch_reduce(edd_problem *p, int nblocks, int stride, int nout, int slot);
 size_t band_solve_lds_bytes(const edd_problem *p, int precision);
-// padding (entries) around band storage; see kernels_band.hip
+// padding (entries) around band storage; see kernels_band.hip and
+// kernels_factor.hip
 constexpr int64_t kBandPadFront = 128;
 int64_t band_pad_back(int max_kd);
+
+// Raise a kernel's dynamic LDS limit to the device's, once per (kernel,
+// device); thread-safe.
+void set_lds_limit_once(const void *kernel, const edd_problem *p);
+
+// Lane `lane`'s value, broadcast to the whole wavefront.
+template <typename T>
+__device__ inline T lane_bcast(T v, int lane);
+template <>
+__device__ inline double lane_bcast<double>(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <>
+__device__ inline float lane_bcast<float>(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
 void element_matrix(int dim, double nu, double *K0);
 double default_theta(int nsub);
 int build_geometry(edd_problem *p, const edd_mesh_desc *d);

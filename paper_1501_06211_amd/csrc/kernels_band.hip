@@ -1,13 +1,11 @@
-// Batched interior solves: band Cholesky factorisation of every subdomain
-// block K_{I_i I_i} and the forward/backward substitutions that apply
+// Batched interior solves: the forward/backward substitutions that apply
 // K_II^{-1} (K_II is the direct sum of the subdomain blocks, eq.
-// (NumberFive); all 2N+1 subproblems of eq. (3MatSplit2) use these solves).
+// (NumberFive); all 2N+1 subproblems of eq. (3MatSplit2) use these solves)
+// with the band factors built in kernels_factor.hip.
 //
 // One workgroup owns one subdomain.  Workgroups are launched largest first
 // (the order array), so that round-robin dispatch over the XCDs spreads the
 // large blocks evenly.
-//
-// Factorisation: left-looking band Cholesky, see k_band_cholesky.
 //
 // Substitution: the whole right-hand side of a subdomain lives in LDS.  The
 // forward sweep reads the factor by columns, the backward sweep a row-major
@@ -25,7 +23,6 @@
 #include "internal.h"
 
 namespace edd {
-namespace {
 
 // Raise a kernel's dynamic LDS limit to the device's, once per (kernel,
 // device); thread-safe.
@@ -39,444 +36,7 @@ void set_lds_limit_once(const void *kernel, const edd_problem *p) {
   done.emplace_back(kernel, p->device);
 }
 
-template <typename T>
-__device__ inline T lane_bcast(T v, int lane);
-template <>
-__device__ inline double lane_bcast<double>(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-template <>
-__device__ inline float lane_bcast<float>(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-// ---------------------------------------------------------------------------
-// Band Cholesky, left-looking.  One thread owns one row of the current
-// window (NB panel columns plus the kd rows below them).  For each panel:
-//   acc[w, c] = A[j0+w, j0+c] - sum_{k < j0} L[j0+w, k] L[j0+c, k]
-// with the L[j0+c, k] (c < NB) staged through LDS in chunks of KC columns
-// and the L[j0+w, k] streamed from the band, then the diagonal block is
-// factored by wavefront 0 (readlane broadcasts) and the rows below solved
-// against it.  Only the panel's own columns are written.
-// ---------------------------------------------------------------------------
-template <int NB, int NT, int KC, int RPT>
-__global__ __launch_bounds__(NT) void k_band_cholesky(
-    const SubDesc *__restrict__ subs, const int *__restrict__ order,
-    double *__restrict__ fac, int *__restrict__ info) {
-  static_assert(NB <= 64, "wavefront 0 factors the diagonal block");
-  __shared__ double U[KC][NB];
-  __shared__ double Dl[NB][NB + 1];
-  __shared__ double Dinv[NB];
-  __shared__ int anybad;
-  const SubDesc s = subs[order[blockIdx.x]];
-  const int n = s.np, kd = s.kd, ld = kd + 1;  // n is a multiple of NB
-  double *L = fac + s.fac_off;
-  const int tid = threadIdx.x;
-  if (tid == 0) anybad = 0;
-
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int W = min(NB + kd, n - j0);
-    // rows w = tid + k*NT of the window are owned by this thread
-    double acc[RPT][NB];
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int w = tid + k * NT;
-      const double *rowp = L + (int64_t)j0 * ld + w;  // (j0+w, j0+c) at rowp + c*kd
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const double v = rowp[c * kd];
-        acc[k][c] = (w < W && c <= w && w - c <= kd) ? v : 0.0;
-      }
-    }
-    // left-looking update from columns [kbeg, j0): each U value read from
-    // LDS serves the RPT rows of the thread
-    const int kbeg = max(0, j0 - kd);
-    const int kfirst = j0 + tid - kd;  // first nonzero column of row tid
-    for (int kc = kbeg; kc < j0; kc += KC) {
-      const int kn = min(KC, j0 - kc);
-      __syncthreads();
-      for (int e = tid; e < KC * NB; e += NT) {
-        const int kk = e / NB, c = e - kk * NB, k = kc + kk;
-        const double v = L[(int64_t)k * ld + (j0 + c - k)];
-        U[kk][c] = (kk < kn && j0 + c - k <= kd) ? v : 0.0;
-      }
-      __syncthreads();
-      if (tid < W && kc + kn > kfirst) {
-        for (int ks = 0; ks < kn; ks += 8) {
-          if (kc + ks + 8 <= kfirst) continue;
-          double lw[RPT][8];
-#pragma unroll
-          for (int k = 0; k < RPT; ++k) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int kk = kc + ks + u;
-              lw[k][u] = L[(int64_t)kk * ld + (j0 + tid + k * NT - kk)];
-            }
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int k = 0; k < RPT; ++k) {
-            const int w = tid + k * NT;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const int kk = kc + ks + u;
-              lw[k][u] = (ks + u < kn && kk >= j0 + w - kd && w < W) ? lw[k][u] : 0.0;
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-              const double uc = U[ks + u][c];
-#pragma unroll
-              for (int k = 0; k < RPT; ++k) acc[k][c] = fma(-lw[k][u], uc, acc[k][c]);
-            }
-          }
-        }
-      }
-    }
-    // Diagonal block: wavefront 0 eliminates the first NB columns of its 64
-    // rows with lane broadcasts and no per-lane predicates.  Rows w < NB end
-    // as the diagonal block of L, rows NB <= w < 64 as final panel rows
-    // (right-looking elimination of a row is its triangular solve); entries
-    // above the diagonal become garbage that is never read or written back.
-    if (tid < 64) {
-      const int w = tid;
-      bool bad = false;
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const double piv = lane_bcast(acc[0][c], c);
-        bad = bad || !(piv > 0.0);
-        const double dc = sqrt(piv > 0.0 ? piv : 1.0);
-        const double rd = 1.0 / dc;
-        acc[0][c] = (w == c) ? dc : acc[0][c] * rd;
-#pragma unroll
-        for (int j = c + 1; j < NB; ++j)
-          acc[0][j] = fma(-acc[0][c], lane_bcast(acc[0][c], j), acc[0][j]);
-        if (w == 0) Dinv[c] = rd;
-      }
-      if (bad && w == 0) anybad = 1;
-      if (w < NB) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) Dl[w][c] = acc[0][c];
-      }
-    }
-    __syncthreads();
-    // all other rows: solve against L_D^T, then write the panel back
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int w = tid + k * NT;
-      if (w < W && w >= 64) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          double x = acc[k][c];
-#pragma unroll
-          for (int c2 = 0; c2 < c; ++c2) x = fma(-acc[k][c2], Dl[c][c2], x);
-          acc[k][c] = x * Dinv[c];
-        }
-      }
-      if (w < W) {
-        double *rowp = L + (int64_t)j0 * ld + w;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c <= w && w - c <= kd) rowp[c * kd] = acc[k][c];
-      }
-    }
-  }
-  __syncthreads();
-  if (tid == 0) info[order[blockIdx.x]] = anybad;
-}
-
-// Band Cholesky for wide windows (more than 512 rows), same panels as
-// k_band_cholesky but with the update
-//   S[w, c] = -sum_{k < j0} L[j0+w, k] L[j0+c, k]
-// on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l supplies
-// A(l%16, l/16) and B(l/16, l%16) and holds C rows l/16 + 4e, column l%16).
-// Wavefront v owns window rows 64v..64v+63 as 4 x 2 tiles of 16 x 16, so a
-// U value read from LDS serves 16 rows instead of one; the A operand streams
-// from the band exactly as before.  Tiles whose 16 rows all lie left of the
-// band for a k-step are skipped.  After the update the tiles pass through
-// LDS, 16 columns at a time, into one row per thread (the transpose buffer
-// reuses the U staging area), and the diagonal block and the row solves
-// proceed as in k_band_cholesky.
-typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int kMxNB = 32, kMxKC = 64, kTransLd = 17;
-
-constexpr int kDlLd = kMxNB + 2;  // 16-byte aligned rows
-constexpr int kMxHead = kMxNB * kDlLd + kMxNB + 64 + 2;  // Dl, Dinv, column, flag
-
-constexpr size_t chol_mfma_lds_bytes(int nt) {
-  // the small arrays first, so that their reads take immediate offsets,
-  // then the transpose area (which also holds the two U buffers)
-  return sizeof(double) * ((size_t)kMxHead + (size_t)nt * kTransLd);
-}
-
-template <int NT>
-__global__ __launch_bounds__(NT) void k_band_cholesky_mfma(
-    const SubDesc *__restrict__ subs, const int *__restrict__ order,
-    double *__restrict__ fac, int *__restrict__ info) {
-  constexpr int NB = kMxNB, KC = kMxKC, NW = NT / 64;
-  constexpr int UPT = KC * NB / NT;  // staged U values per thread
-  static_assert(NT % 64 == 0 && UPT * NT == KC * NB && NT * kTransLd >= 2 * KC * NB,
-                "two U buffers fit the transpose area");
-  extern __shared__ __attribute__((aligned(16))) double lds[];
-  // DlT[c][r] = L_D[r][c] (rows 16-byte aligned: pairs read as one 16-byte load)
-  double (*DlT)[kDlLd] = reinterpret_cast<double (*)[kDlLd]>(lds);
-  double *Dinv = lds + NB * kDlLd;
-  double *col = Dinv + NB;  // one column of the diagonal block, 64 rows
-  int *anybad = reinterpret_cast<int *>(col + 64);
-  double *T = lds + kMxHead;  // NT x kTransLd; the two U buffers alias its start
-  double *Ubuf = T;
-  const SubDesc s = subs[order[blockIdx.x]];
-  const int n = s.np, kd = s.kd, ld = kd + 1;  // n is a multiple of NB
-  double *L = fac + s.fac_off;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar branches
-  const int li = lane & 15, lk = lane >> 4;
-  const int w0 = wave * 64;  // first window row of this wavefront
-  if (tid == 0) *anybad = 0;
-
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int W = min(NB + kd, n - j0);
-    const int kt = j0 + w0 - kd;  // first column reaching row w0
-    // S starts as the panel of A: tile (rt, ct) slot e holds window row
-    // w0 + 16rt + lk + 4e, panel column 16ct + li, at L[j0*ld + w + c*kd]
-    v4d S[4][2];
-    if (w0 < W) {  // wave-uniform
-      const double *pA = L + (int64_t)j0 * ld + (w0 + lk) + (int64_t)li * kd;
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int w = w0 + 16 * rt + lk + 4 * e, c = 16 * ct + li;
-            const double v = pA[16 * rt + 4 * e + (int64_t)16 * ct * kd];
-            S[rt][ct][e] = (w < W && c <= w && w - c <= kd) ? v : 0.0;
-          }
-    } else {
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) S[rt][ct] = v4d{0.0, 0.0, 0.0, 0.0};
-    }
-    const int kbeg = max(0, j0 - kd);
-    // U chunks alternate between two buffers; the next chunk's values are
-    // loaded into registers before the current chunk's products and stored
-    // after them, one barrier per chunk
-    double un[UPT];
-    auto load_u = [&](int kc) {
-      const int kn = min(KC, j0 - kc);
-#pragma unroll
-      for (int q = 0; q < UPT; ++q) {
-        const int e = tid + q * NT, kk = e / NB, c = e - kk * NB, k = kc + kk;
-        const double v = L[(int64_t)k * ld + (j0 + c - k)];
-        un[q] = (kk < kn && j0 + c - k <= kd) ? v : 0.0;
-      }
-    };
-    auto store_u = [&](double *Ub) {
-#pragma unroll
-      for (int q = 0; q < UPT; ++q) Ub[tid + q * NT] = un[q];
-    };
-    __syncthreads();  // the previous panel's columns are written back
-    if (kbeg < j0) {
-      load_u(kbeg);
-      store_u(Ubuf);
-    }
-    int par = 0;
-    for (int kc = kbeg; kc < j0; kc += KC, par ^= 1) {
-      const int kn = min(KC, j0 - kc);
-      __syncthreads();  // chunk kc visible; the other buffer's readers are done
-      const bool more = kc + KC < j0;
-      if (more) load_u(kc + KC);
-      const double(*U)[NB] = reinterpret_cast<const double(*)[NB]>(Ubuf + par * KC * NB);
-      // batches of 8 columns from the first that reaches row w0
-      const int ks0 = kt - kc >= 8 ? ((kt - kc) & ~7) : 0;
-      if (w0 < W && kc + kn > kt && ks0 < kn) {  // wave-uniform
-        // (j0+w, k) sits at L[k*ld + j0+w-k] = L[k*kd + j0+w]: one lane
-        // pointer, +16 per row tile and +4*kd per k-step
-        const double *pa = L + (int64_t)(kc + lk) * kd + (j0 + w0 + li);
-        const int lead = kc + lk + kd - j0 - w0 - li;  // row offset of the band edge
-        double an[2][4];
-        auto load_a = [&](int ks) {
-          const double *pk = pa + ks * kd;
-#pragma unroll
-          for (int st = 0; st < 2; ++st)
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) an[st][rt] = pk[st * 4 * kd + 16 * rt];
-        };
-        load_a(ks0);
-        for (int ks = ks0; ks < kn; ks += 8) {
-          double a[2][4], b[2][2];
-#pragma unroll
-          for (int st = 0; st < 2; ++st)
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) a[st][rt] = an[st][rt];
-          if (ks + 8 < kn) load_a(ks + 8);  // in flight during this batch
-#pragma unroll
-          for (int st = 0; st < 2; ++st)
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) b[st][ct] = U[ks + 4 * st + lk][16 * ct + li];
-#pragma unroll
-          for (int st = 0; st < 2; ++st)
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-              // kept: k < j0 (inside this chunk), j0+w-k <= kd, w < W
-              const bool in = ks + 4 * st + lk < kn && lead + ks + 4 * st >= 16 * rt &&
-                              w0 + 16 * rt + li < W;
-              a[st][rt] = in ? -a[st][rt] : 0.0;
-            }
-#pragma unroll
-          for (int st = 0; st < 2; ++st)
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-              if (kc + ks + 4 * st + 4 <= kt + 16 * rt) continue;  // tile left of the band
-#pragma unroll
-              for (int ct = 0; ct < 2; ++ct)
-                S[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][rt], b[st][ct],
-                                                                  S[rt][ct], 0, 0, 0);
-            }
-        }
-      }
-      if (more) store_u(Ubuf + (par ^ 1) * KC * NB);
-    }
-    // tiles -> one window row per thread (16 columns at a time)
-    double acc[NB];
-    double *Tw = T + w0 * kTransLd;
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      __syncthreads();  // U (first half) or the previous half is consumed
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Tw[(16 * rt + lk + 4 * e) * kTransLd + li] = S[rt][ct][e];
-      __syncthreads();
-#pragma unroll
-      for (int c = 0; c < 16; ++c) acc[16 * ct + c] = Tw[lane * kTransLd + c];
-    }
-    const int w = tid;
-    // Diagonal block by wavefront 0 (rows 0..63 of the window, right-looking
-    // as in k_band_cholesky).  Each scaled column goes through LDS and is
-    // read back as broadcasts; 1/sqrt of the pivot is the hardware estimate
-    // refined by two Newton steps, y <- y + y (1 - p y^2) / 2 (each squares
-    // the relative error).
-    if (tid < 64) {
-      bool bad = false;
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const double piv = lane_bcast(acc[c], c);
-        bad = bad || !(piv > 0.0);
-        const double pv = piv > 0.0 ? piv : 1.0;
-        double y = __builtin_amdgcn_rsq(pv);
-#pragma unroll
-        for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-pv * y, y, 1.0), y);
-        const double rd = y, dc = pv * y;
-        acc[c] = (w == c) ? dc : acc[c] * rd;
-        if (w == 0) Dinv[c] = rd;
-        if (w < NB) DlT[c][w] = acc[c];
-        if (c + 1 < NB) {
-          col[w] = acc[c];
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          const double2 *col2 = reinterpret_cast<const double2 *>(col);
-#pragma unroll
-          for (int q = (c + 1) / 2; q < NB / 2; ++q) {
-            const double2 v = col2[q];
-            if (2 * q > c) acc[2 * q] = fma(-acc[c], v.x, acc[2 * q]);
-            acc[2 * q + 1] = fma(-acc[c], v.y, acc[2 * q + 1]);
-            // keep the update here (not sunk to the column's pivot, which
-            // would hold every broadcast value live across the loop)
-            asm volatile("" : "+v"(acc[2 * q]), "+v"(acc[2 * q + 1]));
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();  // all reads done before the next column is stored
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-      }
-      if (bad && w == 0) *anybad = 1;
-    }
-    __syncthreads();
-    // rows below: solve x L_D^T = a, right-looking over the columns of L_D
-    if (w < W && w >= 64) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        acc[c] *= Dinv[c];
-        const double2 *d2 = reinterpret_cast<const double2 *>(DlT[c]);
-#pragma unroll
-        for (int q = (c + 1) / 2; q < NB / 2; ++q) {
-          const double2 v = d2[q];
-          if (2 * q > c) acc[2 * q] = fma(-acc[c], v.x, acc[2 * q]);
-          acc[2 * q + 1] = fma(-acc[c], v.y, acc[2 * q + 1]);
-          if (q % 2 == 1) __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-    }
-    if (w < W) {
-      double *rowp = L + (int64_t)j0 * ld + w;
-#pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c <= w && w - c <= kd) rowp[c * kd] = acc[c];
-    }
-  }
-  __syncthreads();
-  if (tid == 0) info[order[blockIdx.x]] = *anybad;
-}
-
-// Solve layouts from the factor L (column band, true diagonal):
-//   Cs[p*ld + r] = L[p+r, p] with the diagonal replaced by 1/L[p,p]
-//   Rs[q*ld + k] = L[q, q-k]  with the diagonal replaced by 1/L[q,q]
-// Cs may alias L (then only its diagonals change).  Work comes in 64x64
-// tiles (rows q or p, offsets k or r) per subdomain; a row-layout tile's
-// sources (q-k, k) lie on a skewed band of the column layout and are read
-// along k (contiguous within a column) into LDS, then written along k.
-// The only in-place change, the diagonal of column p, is read solely by
-// the row-layout tile of the same rows at offsets [0, 64), which writes it.
-template <typename T>
-__global__ __launch_bounds__(256) void k_solve_layouts(
-    const SubDesc *__restrict__ subs, const double *__restrict__ Lf,
-    T *__restrict__ Cs, T *__restrict__ Rs) {
-  __shared__ double tile[64][65];
-  const SubDesc s = subs[blockIdx.y];
-  const int n = s.np, kd = s.kd, ld = kd + 1;
-  const double *Lb = Lf + s.fac_off;
-  T *Cb = Cs + s.fac_off;
-  T *Rb = Rs + s.fac_off;
-  const bool inplace = (const void *)Cs == (const void *)Lf;
-  const int nqt = n / 64, nkt = (ld + 63) / 64;
-  for (int t = blockIdx.x; t < nqt * nkt; t += gridDim.x) {
-    const int q0 = (t / nkt) * 64, k0 = (t % nkt) * 64;
-    const int pmin = q0 - k0 - 63;  // sources p = q - k of this tile
-    for (int e = threadIdx.x; e < 127 * 64; e += blockDim.x) {
-      const int kk = e & 63, p = pmin + (e >> 6), k = k0 + kk, qq = p + k - q0;
-      if (qq < 0 || qq >= 64 || k >= ld) continue;
-      double v = p >= 0 ? Lb[(int64_t)p * ld + k] : 0.0;
-      if (k == 0) v = 1.0 / v;
-      tile[qq][kk] = v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-      const int qq = e >> 6, k = k0 + (e & 63);
-      if (k < ld) Rb[(int64_t)(q0 + qq) * ld + k] = (T)tile[qq][e & 63];
-    }
-    if (!inplace) {
-      for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-        const int pp = e >> 6, r = k0 + (e & 63);
-        if (r >= ld) continue;
-        double v = Lb[(int64_t)(q0 + pp) * ld + r];
-        if (r == 0) v = 1.0 / v;
-        Cb[(int64_t)(q0 + pp) * ld + r] = (T)v;
-      }
-    } else if (k0 == 0) {
-      for (int pp = threadIdx.x; pp < 64; pp += blockDim.x)
-        Cb[(int64_t)(q0 + pp) * ld] = (T)(1.0 / Lb[(int64_t)(q0 + pp) * ld]);
-    }
-    __syncthreads();  // the tile is reused by the next iteration
-  }
-}
+namespace {
 
 // ---------------------------------------------------------------------------
 // Substitutions.  Block b of 64 rows is owned by wavefront b mod NW (row i
@@ -855,126 +415,6 @@ void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, 
 // rows of half h (the plane next to S), and so is W_h.
 // ---------------------------------------------------------------------------
 
-// W_h = L_h,tail^{-1} B_h in place (B_h as assembled), from the true-diagonal
-// factor (before the solve layouts are built).  A block owns 64 columns and
-// walks the rows in 64-row blocks: the block's rows minus L(block, earlier)
-// times the finished earlier rows (64x64 tiles through LDS), then a
-// triangular solve with the diagonal tile, one thread per column.
-__global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ subs,
-                                                  const SepDesc *__restrict__ seps,
-                                                  const double *__restrict__ fac,
-                                                  double *__restrict__ W) {
-  const SepDesc sd = seps[blockIdx.y >> 1];
-  const int h = blockIdx.y & 1;
-  const SubDesc leaf = subs[h ? sd.b : sd.a];
-  const int ns = sd.ns, ld = leaf.kd + 1, t0 = leaf.n - ns;
-  const double *L = fac + leaf.fac_off;
-  double *Wh = W + sd.w_off + (int64_t)h * ns * ns;
-  const int c0 = blockIdx.x * 64;
-  if (c0 >= ns) return;
-  __shared__ double Lt[64][65], Xt[64][65];
-  const int tid = threadIdx.x, col = tid & 63, rg = tid >> 6;  // rows rg*16 .. +16
-  // L(t0 + a, t0 + b) for a >= b, 0 otherwise
-  auto Lat = [&](int a, int b) -> double {
-    if (a < b || a >= ns || b >= ns) return 0.0;
-    const int r = t0 + a, c = t0 + b;
-    return L[(int64_t)c * ld + (r - c)];
-  };
-  const int nrb = (ns + 63) / 64;
-  for (int qb = 0; qb < nrb; ++qb) {
-    const int q0 = qb * 64;
-    double acc[16];
-#pragma unroll
-    for (int a = 0; a < 16; ++a) {
-      const int q = q0 + rg * 16 + a, j = c0 + col;
-      acc[a] = (q < ns && j < ns) ? Wh[(int64_t)q * ns + j] : 0.0;
-    }
-    for (int pb = 0; pb < qb; ++pb) {
-      const int p0 = pb * 64;
-      __syncthreads();
-      for (int e2 = tid; e2 < 64 * 64; e2 += 256) {
-        const int a = e2 >> 6, b = e2 & 63;
-        Lt[a][b] = Lat(q0 + a, p0 + b);
-        const int pr = p0 + a, j = c0 + b;
-        Xt[a][b] = (pr < ns && j < ns) ? Wh[(int64_t)pr * ns + j] : 0.0;
-      }
-      __syncthreads();
-      for (int b = 0; b < 64; ++b) {
-        const double x = Xt[b][col];
-#pragma unroll
-        for (int a = 0; a < 16; ++a) acc[a] = fma(-Lt[rg * 16 + a][b], x, acc[a]);
-      }
-    }
-    __syncthreads();
-    for (int e2 = tid; e2 < 64 * 64; e2 += 256) {
-      const int a = e2 >> 6, b = e2 & 63;
-      Lt[a][b] = Lat(q0 + a, q0 + b);
-    }
-#pragma unroll
-    for (int a = 0; a < 16; ++a) Xt[rg * 16 + a][col] = acc[a];
-    __syncthreads();
-    if (tid < 64) {
-      const int j = c0 + tid;
-      for (int a = 0; a < 64 && q0 + a < ns; ++a) {
-        double v = Xt[a][tid];
-        for (int b = 0; b < a; ++b) v = fma(-Lt[a][b], Xt[b][tid], v);
-        v /= Lt[a][a];
-        Xt[a][tid] = v;
-        if (j < ns) Wh[(int64_t)(q0 + a) * ns + j] = v;
-      }
-    }
-  }
-}
-
-// Separator block (band storage with kd = ns - 1, C as assembled) minus
-// W_a^T W_a + W_b^T W_b, lower triangle; 32x32 output tiles.
-__global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ subs,
-                                                  const SepDesc *__restrict__ seps,
-                                                  const double *__restrict__ W,
-                                                  double *__restrict__ fac) {
-  const SepDesc sd = seps[blockIdx.y];
-  const int ns = sd.ns;
-  const int nt = (ns + 31) / 32;
-  // blockIdx.x enumerates the lower-triangle tiles (tq >= tp)
-  int tq = 0, rem = blockIdx.x;
-  while (rem > tq) { rem -= tq + 1; ++tq; }
-  const int tp = rem;
-  if (tq >= nt) return;
-  const SubDesc S = subs[sd.s];
-  const int ld = S.kd + 1;
-  __shared__ double Aq[32][33], Ap[32][33];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  for (int h = 0; h < 2; ++h) {
-    const double *Wh = W + sd.w_off + (int64_t)h * ns * ns;
-    for (int k0 = 0; k0 < ns; k0 += 32) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-        const int kk = e >> 5, c = e & 31, k = k0 + kk;
-        const int q = tq * 32 + c, pcol = tp * 32 + c;
-        Aq[kk][c] = (k < ns && q < ns) ? Wh[(int64_t)k * ns + q] : 0.0;
-        Ap[kk][c] = (k < ns && pcol < ns) ? Wh[(int64_t)k * ns + pcol] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int kk = 0; kk < 32; ++kk)
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int c = 0; c < 2; ++c)
-            acc[a][c] = fma(Aq[kk][ty * 2 + a], Ap[kk][tx * 2 + c], acc[a][c]);
-    }
-  }
-  double *band = fac + S.fac_off;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int q = tq * 32 + ty * 2 + a, pcol = tp * 32 + tx * 2 + c;
-      if (q < ns && pcol <= q) band[(int64_t)pcol * ld + (q - pcol)] -= acc[a][c];
-    }
-}
-
 // x_S = b_S - W_a^T y_a,tail - W_b^T y_b,tail (y in x); 64 columns per block,
 // rows split over the sixteen wavefronts, eight rows a batch per lane (eight
 // loads in flight), and summed in a fixed order.
@@ -1073,26 +513,6 @@ __global__ __launch_bounds__(256) void k_sep_update(const SubDesc *__restrict__ 
   }
 }
 
-__global__ void k_f64_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
-}
-
-template <int NT, int RPT>
-void chol_launch(edd_problem *p, const int *order, int count) {
-  if (count <= 0) return;
-  k_band_cholesky<32, NT, 64, RPT><<<count, NT, 0, p->stream>>>(
-      p->subs_d, order, p->fac64_d, p->info_d);
-}
-
-template <int NT>
-void chol_launch_mfma(edd_problem *p, const int *order, int count) {
-  if (count <= 0) return;
-  set_lds_limit_once((const void *)k_band_cholesky_mfma<NT>, p);
-  k_band_cholesky_mfma<NT><<<count, NT, chol_mfma_lds_bytes(NT), p->stream>>>(
-      p->subs_d, order, p->fac64_d, p->info_d);
-}
-
 template <typename T, typename W, int NT>
 void solve_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x) {
   const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
@@ -1111,50 +531,6 @@ int64_t band_pad_back(int max_kd) {
 size_t band_solve_lds_bytes(const edd_problem *p, int precision) {
   (void)precision;  // both paths keep the right-hand side in FP64
   return ((8 * (size_t)p->max_np + 15) / 16) * 16;
-}
-
-static void cholesky_subset(edd_problem *p, const int *order, int count) {
-  const int rows = 32 + p->max_kd;  // window rows
-  if (rows <= 64) chol_launch<64, 1>(p, order, count);
-  else if (rows <= 128) chol_launch<128, 1>(p, order, count);
-  else if (rows <= 256) chol_launch<128, 2>(p, order, count);
-  else if (rows <= 512) chol_launch<256, 2>(p, order, count);
-  else if (chol_mfma_lds_bytes(1024) <= p->lds_limit)
-    chol_launch_mfma<1024>(p, order, count);  // kd <= 992 (checked at setup)
-  else chol_launch<1024, 1>(p, order, count);
-}
-
-// Factor every band block; for dissected interiors the halves first, then
-// W_h and the separator's Schur complement, then the separator.
-void launch_band_cholesky(edd_problem *p) {
-  KTimer kt(p, EDD_KT_BAND_CHOLESKY);
-  const int nleaf = p->n_blk - p->n_sep;
-  cholesky_subset(p, p->order_leaf_d, nleaf);
-  if (p->n_sep > 0) {
-    int maxns = 0;
-    for (const SepDesc &sd : p->seps) maxns = std::max(maxns, sd.ns);
-    k_sep_trsm<<<dim3((maxns + 63) / 64, 2 * p->n_sep), 256, 0, p->stream>>>(
-        p->subs_d, p->seps_d, p->fac64_d, p->W64_d);
-    const int nt = (maxns + 31) / 32;
-    k_sep_syrk<<<dim3(nt * (nt + 1) / 2, p->n_sep), 256, 0, p->stream>>>(
-        p->subs_d, p->seps_d, p->W64_d, p->fac64_d);
-    cholesky_subset(p, p->order_sep_d, p->n_sep);
-  }
-}
-
-// After the factorisation: build the solve layouts (FP64 always, FP32 when
-// requested).  The FP64 column layout overwrites the factor in place.
-void launch_band_layouts(edd_problem *p) {
-  KTimer kt(p, EDD_KT_LAYOUTS);
-  dim3 grid(64, p->n_blk);
-  if (p->n_sep > 0 && p->W32_d)
-    k_f64_to_f32<<<(unsigned)((p->w_entries + 255) / 256), 256, 0, p->stream>>>(
-        p->w_entries, p->W64_d, p->W32_d);
-  if (p->fac32_d)
-    k_solve_layouts<float><<<grid, 256, 0, p->stream>>>(p->subs_d, p->fac64_d,
-                                                        p->fac32_d, p->rac32_d);
-  k_solve_layouts<double><<<grid, 256, 0, p->stream>>>(p->subs_d, p->fac64_d,
-                                                       p->fac64_d, p->rac64_d);
 }
 
 // Substitution variants (the tile shapes the autotuner chooses between):
