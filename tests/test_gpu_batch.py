@@ -100,6 +100,34 @@ def test_wide_variants_at_half_bandwidths_past_448(variant, dissect):
     prob.close()
 
 
+@pytest.mark.parametrize("ny,kd,dissect", [(12, 509, 0), (12, 509, 1), (11, 473, 0), (11, 473, 1)])
+def test_factor_windows_either_side_of_the_matrix_core_switch(ny, kd, dissect):
+    """Factor windows of 541 rows (32 + kd 509: the matrix-core Cholesky,
+    with fewer row tiles than four per wavefront) and of 505 rows (kd 473:
+    the last vector configuration); dissected separators are dense blocks
+    factored by the same kernel.  The interior solves from those factors
+    against a sparse direct solve."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    rng = np.random.default_rng(ny)
+    p = w.cantilever3d(24, ny, ny, cuts=(np.array([0, 12, 24]), np.array([0, ny]),
+                                         np.array([0, ny])))
+    p.E = 1e-3 + rng.uniform(0, 1, p.n_el) ** 3
+    prob = make_problem(p, dissect=dissect)
+    assert prob.info["max_band"] == kd
+    perm = interior_perm(p, prob)
+    KII, *_ = dd.blocks(p)
+    b = rng.standard_normal(prob.n_interior_dofs)
+    xr = spla.spsolve(KII.tocsc(), b[perm])
+    x = to_np(prob.solve_interior(to_cuda(b)))
+    x32 = to_np(prob.solve_interior(to_cuda(b), precision=edd.F32))
+    e64 = np.linalg.norm(x[perm] - xr) / np.linalg.norm(xr)
+    e32 = np.linalg.norm(x32[perm] - xr) / np.linalg.norm(xr)
+    print(f"kd {kd}, dissect {dissect}: FP64 {e64:.2e}, FP32 factors {e32:.2e}")
+    assert e64 <= 1e-12 and e32 <= 1e-5
+    prob.close()
+
+
 def test_autotune_picks_valid_variants_and_caches():
     require_gpu()
     from paper_1501_06211_amd import edd
