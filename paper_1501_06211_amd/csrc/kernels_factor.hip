@@ -456,7 +456,8 @@ __global__ __launch_bounds__(256) void k_solve_layouts(
 // factor (before the solve layouts are built).  A block owns 64 columns and
 // walks the rows in 64-row blocks: the block's rows minus L(block, earlier)
 // times the finished earlier rows (64x64 tiles through LDS), then a
-// triangular solve with the diagonal tile, one thread per column.
+// triangular solve with the diagonal tile, one column per thread and one
+// 16-row sub-block per wavefront.
 __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ subs,
                                                   const SepDesc *__restrict__ seps,
                                                   const double *__restrict__ fac,
@@ -507,17 +508,38 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
       const int a = e2 >> 6, b = e2 & 63;
       Lt[a][b] = Lat(q0 + a, q0 + b);
     }
-#pragma unroll
-    for (int a = 0; a < 16; ++a) Xt[rg * 16 + a][col] = acc[a];
     __syncthreads();
-    if (tid < 64) {
-      const int j = c0 + tid;
-      for (int a = 0; a < 64 && q0 + a < ns; ++a) {
-        double v = Xt[a][tid];
-        for (int b = 0; b < a; ++b) v = fma(-Lt[a][b], Xt[b][tid], v);
-        v /= Lt[a][a];
-        Xt[a][tid] = v;
-        if (j < ns) Wh[(int64_t)(q0 + a) * ns + j] = v;
+    // Forward substitution with the diagonal tile in 16-row sub-blocks: the
+    // wavefront owning sub-block sb solves its rows in registers (unrolled),
+    // publishes them through LDS, and the wavefronts below subtract them.
+    // Row a still takes its earlier rows in the order 0, 1, ..., a-1.
+    const int j = c0 + col;
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      if (rg == sb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int r = 16 * sb + i;
+          double v = acc[i];
+#pragma unroll
+          for (int k = 0; k < i; ++k) v = fma(-Lt[r][16 * sb + k], acc[k], v);
+          acc[i] = q0 + r < ns ? v / Lt[r][r] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int q = q0 + 16 * sb + i;
+          Xt[16 * sb + i][col] = acc[i];
+          if (q < ns && j < ns) Wh[(int64_t)q * ns + j] = acc[i];
+        }
+      }
+      __syncthreads();
+      if (rg > sb) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const double x = Xt[16 * sb + k][col];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[i] = fma(-Lt[16 * rg + i][16 * sb + k], x, acc[i]);
+        }
       }
     }
   }
