@@ -285,27 +285,40 @@ __device__ inline double pair_entry(const Geom &g, const double *__restrict__ K0
 // One thread per stored band entry (column p, offset r) of every band block:
 // K[q, p] with q = p + r, summed over the elements shared by the two nodes;
 // padding columns p >= n get an identity diagonal.
+//
+// Most entries of the band are structural zeros.  A block numbers its nodes
+// with strides 1, len0 and len0*len1, so two nodes can only be neighbours if
+// their index difference d (>= 0 here) is within one of 0, len0 or, in 3D,
+// len0*len1 of a multiple in {-1, 0, 1}; every other entry is zero without
+// decoding coordinates.  Candidates still go through the full test, so the
+// band is the same as with it alone.  A block's entries fit 32-bit indices.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_assemble_band(
     Geom g, const double *__restrict__ K0, const double *__restrict__ E,
     const SubDesc *__restrict__ subs, double *__restrict__ fac) {
   const SubDesc s = subs[blockIdx.y];
   const int ld = s.kd + 1;
-  const int64_t total = (int64_t)s.np * ld;
+  const int total = s.np * ld;
+  const int l0 = s.len[0], plane = s.len[0] * s.len[1];
+  auto near = [&](int t) {  // t = dx + l0 dy with |dx|, |dy| <= 1 possible
+    return (t >= -1 && t <= 1) || (t >= l0 - 1 && t <= l0 + 1) || (t >= -l0 - 1 && t <= -l0 + 1);
+  };
   double *band = fac + s.fac_off;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int p = (int)(e / ld);
-    const int r = (int)(e - (int64_t)p * ld);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int p = e / ld;
+    const int r = e - p * ld;
     const int q = p + r;
     double val = 0.0;
     if (p >= s.n) {
       val = r == 0 ? 1.0 : 0.0;  // identity padding rows
     } else if (q < s.n) {
-      int x1[3], x2[3], c1, c2;
-      block_coords(s, D, p, x1, c1);
-      block_coords(s, D, q, x2, c2);
-      val = pair_entry<D>(g, K0, E, x1, c1, x2, c2);
+      const int d = q / D - p / D;
+      if (near(d) || (D == 3 && near(d - plane))) {
+        int x1[3], x2[3], c1, c2;
+        block_coords(s, D, p, x1, c1);
+        block_coords(s, D, q, x2, c2);
+        val = pair_entry<D>(g, K0, E, x1, c1, x2, c2);
+      }
     }
     band[e] = val;
   }
