@@ -417,12 +417,25 @@ __global__ __launch_bounds__(256) void k_solve_layouts(
   for (int t = blockIdx.x; t < nqt * nkt; t += gridDim.x) {
     const int q0 = (t / nkt) * 64, k0 = (t % nkt) * 64;
     const int pmin = q0 - k0 - 63;  // sources p = q - k of this tile
-    for (int e = threadIdx.x; e < 127 * 64; e += blockDim.x) {
+    // all of a thread's loads first (addresses of unused slots clamped to
+    // the block's first entry), then the LDS writes
+    constexpr int kSlots = (127 * 64 + 255) / 256;
+    double v[kSlots];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+      const int e = threadIdx.x + 256 * j;
       const int kk = e & 63, p = pmin + (e >> 6), k = k0 + kk, qq = p + k - q0;
-      if (qq < 0 || qq >= 64 || k >= ld) continue;
-      double v = p >= 0 ? Lb[(int64_t)p * ld + k] : 0.0;
-      if (k == 0) v = 1.0 / v;
-      tile[qq][kk] = v;
+      const bool in = e < 127 * 64 && qq >= 0 && qq < 64 && k < ld && p >= 0;
+      v[j] = Lb[in ? (int64_t)p * ld + k : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      const int kk = e & 63, p = pmin + (e >> 6), k = k0 + kk, qq = p + k - q0;
+      if (e >= 127 * 64 || qq < 0 || qq >= 64 || k >= ld) continue;
+      double x = p >= 0 ? v[j] : 0.0;
+      if (k == 0) x = 1.0 / x;
+      tile[qq][kk] = x;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
@@ -430,12 +443,18 @@ __global__ __launch_bounds__(256) void k_solve_layouts(
       if (k < ld) Rb[(int64_t)(q0 + qq) * ld + k] = (T)tile[qq][e & 63];
     }
     if (!inplace) {
-      for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-        const int pp = e >> 6, r = k0 + (e & 63);
+      double c[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int e = threadIdx.x + 256 * j, pp = e >> 6, r = k0 + (e & 63);
+        c[j] = Lb[r < ld ? (int64_t)(q0 + pp) * ld + r : 0];
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int e = threadIdx.x + 256 * j, pp = e >> 6, r = k0 + (e & 63);
         if (r >= ld) continue;
-        double v = Lb[(int64_t)(q0 + pp) * ld + r];
-        if (r == 0) v = 1.0 / v;
-        Cb[(int64_t)(q0 + pp) * ld + r] = (T)v;
+        const double x = r == 0 ? 1.0 / c[j] : c[j];
+        Cb[(int64_t)(q0 + pp) * ld + r] = (T)x;
       }
     } else if (k0 == 0) {
       for (int pp = threadIdx.x; pp < 64; pp += blockDim.x)
