@@ -491,11 +491,11 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
   if (c0 >= ns) return;
   __shared__ double Lt[64][65], Xt[64][65];
   const int tid = threadIdx.x, col = tid & 63, rg = tid >> 6;  // rows rg*16 .. +16
-  // L(t0 + a, t0 + b) for a >= b, 0 otherwise
-  auto Lat = [&](int a, int b) -> double {
-    if (a < b || a >= ns || b >= ns) return 0.0;
-    const int r = t0 + a, c = t0 + b;
-    return L[(int64_t)c * ld + (r - c)];
+  // L(t0 + a, t0 + b) for a >= b, 0 otherwise; a thread loads its 16 values
+  // of a tile together (unused slots read the block's first entry)
+  auto in_L = [&](int a, int b) { return a >= b && a < ns && b < ns; };
+  auto idx_L = [&](int a, int b) -> int64_t {
+    return in_L(a, b) ? (int64_t)(t0 + b) * ld + (a - b) : 0;
   };
   const int nrb = (ns + 63) / 64;
   for (int qb = 0; qb < nrb; ++qb) {
@@ -508,12 +508,21 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
     }
     for (int pb = 0; pb < qb; ++pb) {
       const int p0 = pb * 64;
-      __syncthreads();
-      for (int e2 = tid; e2 < 64 * 64; e2 += 256) {
-        const int a = e2 >> 6, b = e2 & 63;
-        Lt[a][b] = Lat(q0 + a, p0 + b);
+      double vl[16], vx[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e2 = tid + 256 * i, a = e2 >> 6, b = e2 & 63;
         const int pr = p0 + a, j = c0 + b;
-        Xt[a][b] = (pr < ns && j < ns) ? Wh[(int64_t)pr * ns + j] : 0.0;
+        vl[i] = L[idx_L(q0 + a, p0 + b)];
+        vx[i] = Wh[(pr < ns && j < ns) ? (int64_t)pr * ns + j : 0];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e2 = tid + 256 * i, a = e2 >> 6, b = e2 & 63;
+        const int pr = p0 + a, j = c0 + b;
+        Lt[a][b] = in_L(q0 + a, p0 + b) ? vl[i] : 0.0;
+        Xt[a][b] = (pr < ns && j < ns) ? vx[i] : 0.0;
       }
       __syncthreads();
       for (int b = 0; b < 64; ++b) {
@@ -522,10 +531,19 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
         for (int a = 0; a < 16; ++a) acc[a] = fma(-Lt[rg * 16 + a][b], x, acc[a]);
       }
     }
-    __syncthreads();
-    for (int e2 = tid; e2 < 64 * 64; e2 += 256) {
-      const int a = e2 >> 6, b = e2 & 63;
-      Lt[a][b] = Lat(q0 + a, q0 + b);
+    {
+      double vl[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e2 = tid + 256 * i, a = e2 >> 6, b = e2 & 63;
+        vl[i] = L[idx_L(q0 + a, q0 + b)];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int e2 = tid + 256 * i, a = e2 >> 6, b = e2 & 63;
+        Lt[a][b] = in_L(q0 + a, q0 + b) ? vl[i] : 0.0;
+      }
     }
     __syncthreads();
     // Forward substitution with the diagonal tile in 16-row sub-blocks: the
@@ -586,12 +604,22 @@ __global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ su
   for (int h = 0; h < 2; ++h) {
     const double *Wh = W + sd.w_off + (int64_t)h * ns * ns;
     for (int k0 = 0; k0 < ns; k0 += 32) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-        const int kk = e >> 5, c = e & 31, k = k0 + kk;
+      // a thread's eight loads first (unused slots read the first entry)
+      double vq[4], vp[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = threadIdx.x + 256 * j, kk = e >> 5, c = e & 31, k = k0 + kk;
         const int q = tq * 32 + c, pcol = tp * 32 + c;
-        Aq[kk][c] = (k < ns && q < ns) ? Wh[(int64_t)k * ns + q] : 0.0;
-        Ap[kk][c] = (k < ns && pcol < ns) ? Wh[(int64_t)k * ns + pcol] : 0.0;
+        vq[j] = Wh[(k < ns && q < ns) ? (int64_t)k * ns + q : 0];
+        vp[j] = Wh[(k < ns && pcol < ns) ? (int64_t)k * ns + pcol : 0];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = threadIdx.x + 256 * j, kk = e >> 5, c = e & 31, k = k0 + kk;
+        const int q = tq * 32 + c, pcol = tp * 32 + c;
+        Aq[kk][c] = (k < ns && q < ns) ? vq[j] : 0.0;
+        Ap[kk][c] = (k < ns && pcol < ns) ? vp[j] : 0.0;
       }
       __syncthreads();
 #pragma unroll 8
