@@ -304,9 +304,13 @@ __global__ __launch_bounds__(kBlock) void k_assemble_band(
     return (t >= -1 && t <= 1) || (t >= l0 - 1 && t <= l0 + 1) || (t >= -l0 - 1 && t <= -l0 + 1);
   };
   double *band = fac + s.fac_off;
+  const double rld = 1.0 / ld;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int p = e / ld;
-    const int r = e - p * ld;
+    // e / ld from the FP64 reciprocal: off by at most one, then corrected
+    int p = (int)((double)e * rld);
+    int r = e - p * ld;
+    if (r < 0) { --p; r += ld; }
+    if (r >= ld) { ++p; r -= ld; }
     const int q = p + r;
     double val = 0.0;
     if (p >= s.n) {
