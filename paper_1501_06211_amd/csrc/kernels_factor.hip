@@ -151,18 +151,19 @@ __global__ __launch_bounds__(NT) void k_band_cholesky(
   if (tid == 0) info[order[blockIdx.x]] = anybad;
 }
 
-// Band Cholesky for wide windows (more than 512 rows), same panels as
-// k_band_cholesky but with the update
-//   S[w, c] = -sum_{k < j0} L[j0+w, k] L[j0+c, k]
+// Band Cholesky for wide windows (more than 512 rows): the same left-looking
+// 32-column panels as k_band_cholesky, with the update
+//   S[w, c] = A[j0+w, j0+c] - sum_{k < j0} L[j0+w, k] L[j0+c, k]
 // on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l supplies
 // A(l%16, l/16) and B(l/16, l%16) and holds C rows l/16 + 4e, column l%16).
-// Each wavefront owns four 16-row tiles of the window (x 2 column tiles of
-// 16), so a U value read from LDS serves 16 rows instead of one; the A
-// operand streams from the band exactly as before.  Tiles whose 16 rows all lie left of the
-// band for a k-step are skipped.  After the update the tiles pass through
-// LDS, 16 columns at a time, into one row per thread (the transpose buffer
-// reuses the U staging area), and the diagonal block and the row solves
-// proceed as in k_band_cholesky.
+// Each wavefront owns four 16-row tiles of the window (times two 16-column
+// tiles), so a U value read from LDS serves 16 rows instead of one; the A
+// operand streams from the band.  Tiles whose rows all lie left of the band
+// for a k-step are skipped.  After the update the tiles pass through LDS, 16
+// columns at a time, into one row per thread (the transpose area also holds
+// the two U buffers).  Wavefront 0 then factors the diagonal block, taking
+// each scaled column back from LDS as broadcasts, and the rows below solve
+// right-looking against it.
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kMxNB = 32, kMxKC = 64, kTransLd = 17;
 
