@@ -655,8 +655,8 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
   EDD_TRY_ALLOC(p->info_d, int, p->n_blk);
   if (p->n_sep > 0) {
     EDD_TRY_ALLOC(p->seps_d, SepDesc, p->n_sep);
-    EDD_TRY_ALLOC(p->W64_d, double, p->w_entries);
-    if (p->factor_precision & EDD_F32) EDD_TRY_ALLOC(p->W32_d, float, p->w_entries);
+    EDD_TRY_ALLOC(p->W64_d, double, p->w_alloc);
+    if (p->factor_precision & EDD_F32) EDD_TRY_ALLOC(p->W32_d, float, p->w_alloc);
   }
   EDD_TRY_ALLOC(p->E_d, double, p->n_el);
   {

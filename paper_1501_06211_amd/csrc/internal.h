@@ -77,7 +77,9 @@ struct PcGraphKey {
 struct SepDesc {
   int a, b, s;
   int ns;
-  int64_t w_off;
+  int ldw;        // row stride of W_h: ns rounded up to 32, so that a row
+                  // segment of a column strip starts on a 128-byte line
+  int64_t w_off;  // W_a at w_off, W_b at w_off + ns * ldw
 };
 
 }  // namespace edd
@@ -105,7 +107,8 @@ struct edd_problem {
   std::vector<int> order_leaf, order_sep;  // halves and whole interiors / separators
   std::vector<edd::SepDesc> seps;
   int n_sep = 0;
-  int64_t w_entries = 0;
+  int64_t w_entries = 0;  // coupling entries, 2 ns^2 per separator
+  int64_t w_alloc = 0;    // entries of the W buffers (rows padded to ldw)
   std::vector<int> inode, gnode, nmap_host;
   int64_t fac_entries = 0;
   int max_kd = 0, max_n = 0, max_np = 0;

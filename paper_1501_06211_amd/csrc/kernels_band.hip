@@ -426,7 +426,7 @@ __global__ __launch_bounds__(1024) void k_sep_rhs(const SubDesc *__restrict__ su
                                                   double *__restrict__ x) {
   constexpr int NWV = 16, U = 8;
   const SepDesc sd = seps[blockIdx.y];
-  const int ns = sd.ns;
+  const int ns = sd.ns, ldw = sd.ldw;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
   __shared__ double part[NWV][64];
@@ -435,16 +435,16 @@ __global__ __launch_bounds__(1024) void k_sep_rhs(const SubDesc *__restrict__ su
     for (int h = 0; h < 2; ++h) {
       const SubDesc leaf = subs[h ? sd.b : sd.a];
       const double *y = x + leaf.dof_off + leaf.n - ns;
-      const T *Wh = W + sd.w_off + (int64_t)h * ns * ns + j;
+      const T *Wh = W + sd.w_off + (int64_t)h * ns * ldw + j;
       int i = wv;
       for (; i + (U - 1) * NWV < ns; i += U * NWV) {
         double wv8[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) wv8[u] = (double)Wh[(int64_t)(i + u * NWV) * ns];
+        for (int u = 0; u < U; ++u) wv8[u] = (double)Wh[(int64_t)(i + u * NWV) * ldw];
 #pragma unroll
         for (int u = 0; u < U; ++u) acc[u & 3] = fma(wv8[u], y[i + u * NWV], acc[u & 3]);
       }
-      for (; i < ns; i += NWV) acc[0] = fma((double)Wh[(int64_t)i * ns], y[i], acc[0]);
+      for (; i < ns; i += NWV) acc[0] = fma((double)Wh[(int64_t)i * ldw], y[i], acc[0]);
     }
   }
   part[wv][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
@@ -474,8 +474,8 @@ __global__ __launch_bounds__(256) void k_sep_update(const SubDesc *__restrict__ 
   const bool two = i + 1 < ns;
   const SubDesc leaf = subs[h ? sd.b : sd.a];
   const SubDesc S = subs[sd.s];
-  const T *r0 = W + sd.w_off + (int64_t)h * ns * ns + (int64_t)i * ns;
-  const T *r1 = two ? r0 + ns : r0;
+  const T *r0 = W + sd.w_off + (int64_t)h * ns * sd.ldw + (int64_t)i * sd.ldw;
+  const T *r1 = two ? r0 + sd.ldw : r0;
   const double *xs = x + S.dof_off;
   double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
   int j = lane;

@@ -487,7 +487,8 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
   const SubDesc leaf = subs[h ? sd.b : sd.a];
   const int ns = sd.ns, ld = leaf.kd + 1, t0 = leaf.n - ns;
   const double *L = fac + leaf.fac_off;
-  double *Wh = W + sd.w_off + (int64_t)h * ns * ns;
+  const int ldw = sd.ldw;
+  double *Wh = W + sd.w_off + (int64_t)h * ns * ldw;
   const int c0 = blockIdx.x * 64;
   if (c0 >= ns) return;
   __shared__ double Lt[64][65], Xt[64][65];
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
       const int q = q0 + rg * 16 + a, j = c0 + col;
-      acc[a] = (q < ns && j < ns) ? Wh[(int64_t)q * ns + j] : 0.0;
+      acc[a] = (q < ns && j < ns) ? Wh[(int64_t)q * ldw + j] : 0.0;
     }
     for (int pb = 0; pb < qb; ++pb) {
       const int p0 = pb * 64;
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
         const int e2 = tid + 256 * i, a = e2 >> 6, b = e2 & 63;
         const int pr = p0 + a, j = c0 + b;
         vl[i] = L[idx_L(q0 + a, p0 + b)];
-        vx[i] = Wh[(pr < ns && j < ns) ? (int64_t)pr * ns + j : 0];
+        vx[i] = Wh[(pr < ns && j < ns) ? (int64_t)pr * ldw + j : 0];
       }
       __syncthreads();
 #pragma unroll
@@ -567,7 +568,7 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
         for (int i = 0; i < 16; ++i) {
           const int q = q0 + 16 * sb + i;
           Xt[16 * sb + i][col] = acc[i];
-          if (q < ns && j < ns) Wh[(int64_t)q * ns + j] = acc[i];
+          if (q < ns && j < ns) Wh[(int64_t)q * ldw + j] = acc[i];
         }
       }
       __syncthreads();
@@ -603,7 +604,7 @@ __global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ su
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int h = 0; h < 2; ++h) {
-    const double *Wh = W + sd.w_off + (int64_t)h * ns * ns;
+    const double *Wh = W + sd.w_off + (int64_t)h * ns * sd.ldw;
     for (int k0 = 0; k0 < ns; k0 += 32) {
       // a thread's eight loads first (unused slots read the first entry)
       double vq[4], vp[4];
@@ -611,8 +612,8 @@ __global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ su
       for (int j = 0; j < 4; ++j) {
         const int e = threadIdx.x + 256 * j, kk = e >> 5, c = e & 31, k = k0 + kk;
         const int q = tq * 32 + c, pcol = tp * 32 + c;
-        vq[j] = Wh[(k < ns && q < ns) ? (int64_t)k * ns + q : 0];
-        vp[j] = Wh[(k < ns && pcol < ns) ? (int64_t)k * ns + pcol : 0];
+        vq[j] = Wh[(k < ns && q < ns) ? (int64_t)k * sd.ldw + q : 0];
+        vp[j] = Wh[(k < ns && pcol < ns) ? (int64_t)k * sd.ldw + pcol : 0];
       }
       __syncthreads();
 #pragma unroll
@@ -699,8 +700,8 @@ void launch_band_layouts(edd_problem *p) {
   KTimer kt(p, EDD_KT_LAYOUTS);
   dim3 grid(64, p->n_blk);
   if (p->n_sep > 0 && p->W32_d)
-    k_f64_to_f32<<<(unsigned)((p->w_entries + 255) / 256), 256, 0, p->stream>>>(
-        p->w_entries, p->W64_d, p->W32_d);
+    k_f64_to_f32<<<(unsigned)((p->w_alloc + 255) / 256), 256, 0, p->stream>>>(
+        p->w_alloc, p->W64_d, p->W32_d);
   if (p->fac32_d)
     k_solve_layouts<float><<<grid, 256, 0, p->stream>>>(p->subs_d, p->fac64_d,
                                                         p->fac32_d, p->rac32_d);

@@ -340,14 +340,14 @@ __global__ __launch_bounds__(kBlock) void k_assemble_coupling(
   const SubDesc leaf = subs[h ? sd.b : sd.a];
   const SubDesc sp = subs[sd.s];
   const int ns = sd.ns;
-  double *out = W + sd.w_off + (int64_t)h * ns * ns;
+  double *out = W + sd.w_off + (int64_t)h * ns * sd.ldw;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)ns * ns;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / ns), j = (int)(e - (int64_t)i * ns);
     int x1[3], x2[3], c1, c2;
     block_coords(leaf, D, leaf.n - ns + i, x1, c1);
     block_coords(sp, D, j, x2, c2);
-    out[e] = pair_entry<D>(g, K0, E, x2, c2, x1, c1);
+    out[(int64_t)i * sd.ldw + j] = pair_entry<D>(g, K0, E, x2, c2, x1, c1);
   }
 }
 

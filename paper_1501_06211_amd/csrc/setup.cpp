@@ -192,7 +192,7 @@ int build_geometry(edd_problem *p, const edd_mesh_desc *d) {
   // band blocks, interior dofs subdomain by subdomain: [half a][half b][sep]
   p->subs.clear();
   p->seps.clear();
-  int64_t dof_off = 0, fac_off = 0, w_off = 0;
+  int64_t dof_off = 0, fac_off = 0, w_off = 0, w_true = 0;
   auto add_block = [&](const Box &bx, int len2, int lo2, int dir, int kind, int sep,
                        bool dense) {
     SubDesc s{};
@@ -230,13 +230,16 @@ int build_geometry(edd_problem *p, const edd_mesh_desc *d) {
     sd.b = add_block(bx, L - mid - 1, lo2 + L - 1, -1, 1, sid, false);
     sd.s = add_block(bx, 1, lo2 + mid, 1, 2, sid, true);
     sd.ns = p->subs[sd.s].n;
+    sd.ldw = (sd.ns + 31) / 32 * 32;
     sd.w_off = w_off;
-    w_off += 2 * (int64_t)sd.ns * sd.ns;
+    w_off += 2 * (int64_t)sd.ns * sd.ldw;
+    w_true += 2 * (int64_t)sd.ns * sd.ns;
     p->seps.push_back(sd);
   }
   p->n_blk = (int)p->subs.size();
   p->n_sep = (int)p->seps.size();
-  p->w_entries = w_off;
+  p->w_entries = w_true;
+  p->w_alloc = w_off;
   p->max_kd = 0;
   p->max_n = 0;
   p->max_np = 0;
