@@ -151,7 +151,7 @@ __global__ __launch_bounds__(NT) void k_band_cholesky(
   if (tid == 0) info[order[blockIdx.x]] = anybad;
 }
 
-// Band Cholesky for wide windows (more than 512 rows): the same left-looking
+// Band Cholesky for windows of more than 128 rows: the same left-looking
 // 32-column panels as k_band_cholesky, with the update
 //   S[w, c] = A[j0+w, j0+c] - sum_{k < j0} L[j0+w, k] L[j0+c, k]
 // on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l supplies
@@ -667,12 +667,13 @@ void chol_launch_mfma(edd_problem *p, const int *order, int count) {
 
 static void cholesky_subset(edd_problem *p, const int *order, int count) {
   const int rows = 32 + p->max_kd;  // window rows
+  // windows over 128 rows on the matrix cores (a wavefront per 64 rows)
+  const bool mx = chol_mfma_lds_bytes(1024) <= p->lds_limit;
   if (rows <= 64) chol_launch<64, 1>(p, order, count);
   else if (rows <= 128) chol_launch<128, 1>(p, order, count);
-  else if (rows <= 256) chol_launch<128, 2>(p, order, count);
-  else if (rows <= 512) chol_launch<256, 2>(p, order, count);
-  else if (chol_mfma_lds_bytes(1024) <= p->lds_limit)
-    chol_launch_mfma<1024>(p, order, count);  // kd <= 992 (checked at setup)
+  else if (rows <= 256) mx ? chol_launch_mfma<256>(p, order, count) : chol_launch<128, 2>(p, order, count);
+  else if (rows <= 512) mx ? chol_launch_mfma<512>(p, order, count) : chol_launch<256, 2>(p, order, count);
+  else if (mx) chol_launch_mfma<1024>(p, order, count);  // kd <= 992 (checked at setup)
   else chol_launch<1024, 1>(p, order, count);
 }
 
