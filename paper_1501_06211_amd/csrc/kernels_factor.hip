@@ -585,7 +585,8 @@ __global__ __launch_bounds__(256) void k_sep_trsm(const SubDesc *__restrict__ su
 }
 
 // Separator block (band storage with kd = ns - 1, C as assembled) minus
-// W_a^T W_a + W_b^T W_b, lower triangle; 32x32 output tiles.
+// W_a^T W_a + W_b^T W_b, lower triangle; 32x32 output tiles, one 16x16
+// quadrant per wavefront on the matrix cores.
 __global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ subs,
                                                   const SepDesc *__restrict__ seps,
                                                   const double *__restrict__ W,
@@ -601,8 +602,12 @@ __global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ su
   const SubDesc S = subs[sd.s];
   const int ld = S.kd + 1;
   __shared__ double Aq[32][33], Ap[32][33];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  // wavefront (rt, ct) owns the 16x16 quadrant at rows 16rt, columns 16ct of
+  // the tile, on the FP64 matrix cores (lane layout as in
+  // k_band_cholesky_mfma): A(i, k) = W[k][q0 + i], B(k, j) = W[k][p0 + j]
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4, rt = wave >> 1, ct = wave & 1;
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
   for (int h = 0; h < 2; ++h) {
     const double *Wh = W + sd.w_off + (int64_t)h * ns * sd.ldw;
     for (int k0 = 0; k0 < ns; k0 += 32) {
@@ -624,23 +629,18 @@ __global__ __launch_bounds__(256) void k_sep_syrk(const SubDesc *__restrict__ su
         Ap[kk][c] = (k < ns && pcol < ns) ? vp[j] : 0.0;
       }
       __syncthreads();
-#pragma unroll 8
-      for (int kk = 0; kk < 32; ++kk)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int c = 0; c < 2; ++c)
-            acc[a][c] = fma(Aq[kk][ty * 2 + a], Ap[kk][tx * 2 + c], acc[a][c]);
+      for (int ks = 0; ks < 32; ks += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Aq[ks + lk][16 * rt + li],
+                                                   Ap[ks + lk][16 * ct + li], acc, 0, 0, 0);
     }
   }
   double *band = fac + S.fac_off;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int q = tq * 32 + ty * 2 + a, pcol = tp * 32 + tx * 2 + c;
-      if (q < ns && pcol <= q) band[(int64_t)pcol * ld + (q - pcol)] -= acc[a][c];
-    }
+  for (int e = 0; e < 4; ++e) {
+    const int q = tq * 32 + 16 * rt + lk + 4 * e, pcol = tp * 32 + 16 * ct + li;
+    if (q < ns && pcol <= q) band[(int64_t)pcol * ld + (q - pcol)] -= acc[e];
+  }
 }
 
 __global__ void k_f64_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
