@@ -244,6 +244,27 @@ int edd_apply_skeleton_op(edd_problem *p, int which, int weighting,
                           const double *x_dev, double *y_dev, double tol,
                           int maxit);
 
+/* ---- allocation-free variant -------------------------------------------
+ * For callers that cannot allocate device memory while they run: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * edd_apply_S_noalloc computes y = S v exactly as edd_apply_S (same kernels,
+ * same order, bitwise equal results), but its interior-length work vector
+ * lives in one static device array of EDD_NOALLOC_MAX_INTERIOR_DOFS doubles
+ * (16 MiB) that every GPU the library runs on holds until the process ends,
+ * instead of the handle's own buffer.  The call allocates nothing and makes
+ * no allocating library call (kernel timing is suspended for its duration).
+ * The handle must come from edd_setup_mesh (which looks up the array's
+ * address on its device) and have moduli set.
+ * Errors: EDD_EINVAL for NULL pointers, a bad precision, or an interior
+ * vector longer than EDD_NOALLOC_MAX_INTERIOR_DOFS (edd_info.
+ * n_interior_dofs); EDD_ESTATE before moduli or without factors of that
+ * precision.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's contents (they are never read): calls that overlap on one GPU
+ * (several streams or host threads) race, and the caller must serialise them. */
+#define EDD_NOALLOC_MAX_INTERIOR_DOFS (1 << 21)
+int edd_apply_S_noalloc(edd_problem *p, const double *v_dev, double *y_dev,
+                        int precision);
+
 /* ---- many problems and tile shapes ------------------------------------ */
 
 /* Solve n independent problems concurrently: a pool of nthreads host

@@ -123,13 +123,16 @@ KTimer::~KTimer() {
   if (p->kt_pending.size() > 4096) kt_resolve(p);
 }
 
-// y = S v on interface vectors
-void apply_S(edd_problem *p, const double *v, double *y, int prec) {
-  double *t = p->w_I[2];
+// y = S v on interface vectors; t is an interior-length work vector
+void apply_S_with(edd_problem *p, const double *v, double *y, int prec, double *t) {
   launch_apply_mapped(p, p->inode_d, p->n_inodes, nullptr, 0.0, v, 1.0, nullptr,
                       1.0, t);
   launch_band_solve(p, prec, t, t);
   launch_apply_mapped(p, p->gnode_d, p->n_gamma, t, -1.0, v, 1.0, nullptr, 1.0, y);
+}
+
+void apply_S(edd_problem *p, const double *v, double *y, int prec) {
+  apply_S_with(p, v, y, prec, p->w_I[2]);
 }
 
 static int ensure_window(edd_problem *p, int cap) {
@@ -634,6 +637,8 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
       p->n_cu = cu;
   }
   rc = build_geometry(p, d);
+  if (rc) { delete p; return rc; }
+  rc = scratch_init(p);
   if (rc) { delete p; return rc; }
   int lds = 0;
   hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);

@@ -217,6 +217,10 @@ struct edd_problem {
 
   int last_hip_error = 0;
 
+  // address of the static work array of edd_apply_S_noalloc on this
+  // handle's device (noalloc.hip)
+  double *scratch_d = nullptr;
+
   // kernel timing (edd_set_kernel_timing)
   bool kt_enabled = false;
   struct Pending { int kind; hipEvent_t a, b; };
@@ -311,6 +315,11 @@ void launch_window_combine(edd_problem *p, int64_t n, int m,
 // scal[slot+1] = ||f||^2
 void launch_residual_norms(edd_problem *p, const double *f, const double *y,
                            int slot);
+
+// y = S v with t (n_idofs doubles) as the interior work vector (api.hip)
+void apply_S_with(edd_problem *p, const double *v, double *y, int prec, double *t);
+// look up the static work array of edd_apply_S_noalloc (noalloc.hip)
+int scratch_init(edd_problem *p);
 
 // preconditioner (kernels_pc.hip)
 int precond_apply(edd_problem *p, const double *r, double *z,

@@ -34,8 +34,9 @@ EXPORTS = [
     "edd_apply_skeleton_op", "edd_cnn_setup", "edd_cnn_num_params",
     "edd_cnn_set_params", "edd_cnn_get_params", "edd_cnn_predict",
     "edd_cnn_loss_grad", "edd_cnn_train_step", "edd_solve_batch", "edd_autotune",
-    "edd_set_solve_variants",
+    "edd_set_solve_variants", "edd_apply_S_noalloc",
 ]
+NOALLOC_MAX_INTERIOR_DOFS = 1 << 21
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
             "precond", "layouts", "band_solve32"]
 
@@ -153,6 +154,7 @@ def lib():
                                       ctypes.POINTER(SolveStats)]
     L.edd_solve_interior.argtypes = [vp, vp, vp, i32]
     L.edd_apply_S.argtypes = [vp, vp, vp, i32]
+    L.edd_apply_S_noalloc.argtypes = [vp, vp, vp, i32]
     L.edd_apply_precond.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts)]
     L.edd_get_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.edd_get_gamma_nodes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
