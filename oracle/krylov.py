@@ -3,9 +3,11 @@
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 
 * ``pcg``: preconditioned conjugate gradients (S is SPD, Section 2).
-* ``fcg``: flexible CG with the Polak-Ribiere choice of beta, for
-  preconditioners that change from one iteration to the next (Section 3
-  uses a flexible Krylov method for the same reason).
+* ``fcg``: flexible CG for preconditioners that change from one iteration
+  to the next (Section 3 uses a flexible Krylov method for the same
+  reason): each new direction is the preconditioned residual made
+  A-orthogonal to the previous directions by explicit Gram-Schmidt (all of
+  them, or the last ``mmax``), then an exact line search along it.
 * ``gmres_right``: GMRES on K P~^{-1} y = f, u = P~^{-1} y (Section 3,
   right preconditioning with the block-triangular P~).
 * ``schur_pcg``: the whole interface solve on the CPU: condensation, Krylov

@@ -175,18 +175,26 @@ def test_batch_matches_single_solves_and_the_oracle():
     fs = [to_cuda(wk.f) for wk in ws]
     us = [torch.zeros_like(f) for f in fs]
     torch.cuda.synchronize()
-    rc, stats = edd.solve_batch(probs, fs, us, tol=1e-10, maxit=4000)
+    # the parity bars (1e-8 on u, 1e-10 on compliance) need the solve at the
+    # tightest residual these high-contrast members reach
+    rc, stats = edd.solve_batch(probs, fs, us, tol=1e-11, maxit=6000)
     torch.cuda.synchronize()
-    assert rc == edd.OK
+    assert rc in (edd.OK, edd.NOT_CONVERGED)
     for wk, prob, f, u, st in zip(ws, probs, fs, us, stats):
-        u1, st1 = prob.solve(f, tol=1e-10, maxit=4000)
+        u1, st1 = prob.solve(f, tol=1e-11, maxit=6000)
         torch.cuda.synchronize()
         assert torch.equal(u, u1), wk.name  # deterministic kernels, same launches
         assert st["iterations"] == st1["iterations"]
         assert st["rel_residual"] <= 1e-10
-    # one member against the oracle's direct solve
-    uref = fe.solve_direct(ws[3])
-    assert np.linalg.norm(to_np(us[3]) - uref) <= 1e-7 * np.linalg.norm(uref)
+    # every member against the oracle's direct solve
+    for wk, u, st in zip(ws, us, stats):
+        uref = fe.solve_direct(wk)
+        cref = fe.compliance(wk.f, uref)
+        err = np.linalg.norm(to_np(u) - uref) / np.linalg.norm(uref)
+        cerr = abs(st["compliance"] - cref) / abs(cref)
+        print(f"  {wk.name}: its={st['iterations']} res={st['rel_residual']:.1e} "
+              f"u_err={err:.1e} c_err={cerr:.1e}")
+        assert err <= 1e-8 and cerr <= 1e-10, wk.name
     lat = [s["t_total_ms"] for s in stats]
     print(f"batch of {len(ws)}: iterations {[s['iterations'] for s in stats]}, "
           f"latency ms {np.round(lat, 1).tolist()}")

@@ -3,9 +3,15 @@ configuration (automatic dissection, autotuned substitution variants).
 
 2D 512x256 SIMP cantilever (263k dofs, 512 subdomains): against the
 oracle's direct solve.  3D 128x64x64 SIMP cantilever (1.6M dofs, 160 uneven
-subdomains): the oracle's element-by-element K apply, its residual of the
-GPU solution, the energy identity, and interior solves of sampled
-subdomains against the oracle's sparse factorisation of that block."""
+subdomains): displacements and compliance against the stored oracle
+reference (tests/golden, written by make_reference.py: the oracle's Schur
+route refined in long double to rel.res 3.6e-15), the oracle's
+element-by-element K apply and its residual of the GPU solution, and
+interior solves of sampled subdomains against the oracle's sparse
+factorisation of that block."""
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -17,6 +23,15 @@ from oracle import fe
 from gpu_util import require_gpu, to_cuda, to_np
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _reference(name):
+    base = os.path.join(GOLDEN, f"{name}_u_ref")
+    with open(base + ".json") as fh:
+        meta = json.load(fh)
+    return np.load(base + ".npy"), meta
 
 
 def _problem(wk):
@@ -83,19 +98,31 @@ def test_3d_128x64x64_properties_and_sampled_interior_blocks():
     ref = fe.apply_K_elementwise(wk, v)
     kerr = np.linalg.norm(y - ref) / np.linalg.norm(ref)
     assert kerr <= 1e-14
-    # the solve, checked by the oracle's own residual and energy identity
+    # displacements and compliance against the stored oracle reference: the
+    # benchmark's own solve (FP64, tol 1e-8), the tightest FP64 solve the
+    # interface iteration reaches, and the mixed path at the benchmark's
+    # switch point; the oracle also recomputes the residual of the GPU u
+    from paper_1501_06211_amd import edd
+    u_ref, meta = _reference(wk.name)
+    assert meta["rel_residual_long_double"] <= 1e-13
+    c_ref = meta["compliance"]
     f = to_cuda(wk.f)
-    u, st = prob.solve(f, tol=1e-8, maxit=5000)
-    un = to_np(u)
-    Ku = fe.apply_K_elementwise(wk, un)
     free = ~fe.dirichlet_dof_mask(wk)
-    r = (wk.f - Ku)[free]
-    rel = np.linalg.norm(r) / np.linalg.norm(wk.f[free])
-    gap = abs(wk.f @ un - un @ Ku)
-    print(f"3D 128x64x64: its={st['iterations']} GPU res={st['rel_residual']:.2e} "
-          f"oracle res={rel:.2e} energy gap={gap:.2e} K apply err={kerr:.1e}")
-    assert rel <= 1.01e-8 and abs(rel - st["rel_residual"]) <= 1e-2 * rel
-    assert gap <= 1.01 * np.linalg.norm(r) * np.linalg.norm(un[free])
+    for label, opts in (("bench FP64 tol 1e-8", dict(tol=1e-8)),
+                        ("FP64 tol 1e-11", dict(tol=1e-11)),
+                        ("mixed, FP32 factors below 1e-3", dict(
+                            tol=1e-8, precision=edd.MODE_RELAXED, mixed_inner_tol=1e-3))):
+        u, st = prob.solve(f, maxit=5000, **opts)
+        un = to_np(u)
+        err = float(np.linalg.norm(un - u_ref) / np.linalg.norm(u_ref))
+        cerr = abs(st["compliance"] - c_ref) / abs(c_ref)
+        r = (wk.f - fe.apply_K_elementwise(wk, un))[free]
+        rel = np.linalg.norm(r) / np.linalg.norm(wk.f[free])
+        print(f"3D 128x64x64 {label}: its={st['iterations']} GPU res={st['rel_residual']:.2e} "
+              f"oracle res={rel:.2e} u_err={err:.2e} c_err={cerr:.2e} flags={st['flags']}")
+        assert abs(rel - st["rel_residual"]) <= 1e-2 * rel
+        assert rel <= 1.01 * opts["tol"] or st["status"] == edd.NOT_CONVERGED
+        assert err <= 1e-8 and cerr <= 1e-10
     # interior solves of sampled subdomains: 16^3 (dissected), 16x16x12,
     # and one touching the clamp
     b = rng.standard_normal(prob.n_interior_dofs)

@@ -138,3 +138,35 @@ def test_features():
     assert np.sqrt(np.mean(X[..., 1:].reshape(-1)[free] ** 2)) == pytest.approx(1.0, rel=1e-14)
     p.E = np.full(p.n_el, 1e-3)
     assert np.all(cnn.features(p, r)[..., 0] == 0.0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_stiffness_indicator_brute_force(dim):
+    """Per node, the mean over the elements that touch it of
+    clip(1 + log10(E_e)/3, 0, 1), by explicit loops over the node grid and
+    the (up to 2^dim) neighbouring element positions, with non-uniform E
+    spanning the clip range."""
+    if dim == 2:
+        p = w.cantilever2d(5, 3, block=5)
+    else:
+        p = w.cantilever3d(4, 3, 2, cuts=([0, 4], [0, 3], [0, 2]))
+    rng = np.random.default_rng(7)
+    E = 10.0 ** rng.uniform(-4.0, 0.5, p.n_el)  # below, inside and above the clip range
+    got = cnn.stiffness_indicator(p, E)
+    nel = list(p.nel) + [1] * (3 - dim)
+    nn = [n + 1 for n in p.nel] + [1] * (3 - dim)
+    want = np.zeros(nn[::-1])
+    for k in range(nn[2]):
+        for j in range(nn[1]):
+            for i in range(nn[0]):
+                vals = []
+                for ek in ((k - 1, k) if dim == 3 else (0,)):
+                    for ej in (j - 1, j):
+                        for ei in (i - 1, i):
+                            if 0 <= ei < nel[0] and 0 <= ej < nel[1] and 0 <= ek < nel[2]:
+                                e = ei + nel[0] * (ej + nel[1] * ek)
+                                vals.append(min(1.0, max(0.0, 1.0 + np.log10(E[e]) / 3.0)))
+                want[k, j, i] = sum(vals) / len(vals)
+    want = want.reshape(got.shape)
+    assert np.allclose(got, want, rtol=0, atol=1e-15)
+    assert got.min() < 0.5 < got.max()
