@@ -76,8 +76,10 @@ extern "C" {
 /* stats.flags bits */
 #define EDD_FLAG_TRUE_RES_RESTART 1 /* recursive residual disagreed; restarted */
 #define EDD_FLAG_MIXED_FALLBACK 2   /* mixed path stalled; fell back to FP64   */
-#define EDD_FLAG_PC_DROPPED 4       /* preconditioner output rejected          */
-#define EDD_FLAG_LEARNED_REJECTED 8 /* network proposal gave no descent; unused */
+#define EDD_FLAG_PC_DROPPED 4       /* reserved: never set (a step without     */
+                                    /* descent ends the solve, EDD_EBREAKDOWN) */
+#define EDD_FLAG_LEARNED_REJECTED 8 /* the network's proposal was dropped: its */
+                                    /* interface energy <d,Sd> was not positive */
 
 typedef struct edd_problem edd_problem;
 
@@ -327,6 +329,16 @@ int edd_cnn_loss_grad(edd_problem *p, const double *E_dev, const double *r_dev,
  * the loss before the step. */
 int edd_cnn_train_step(edd_problem *p, const double *E_dev, const double *r_dev,
                        const double *e_dev, double lr, double *loss);
+
+/* Training pair of one warm-started step of a moduli sequence: with the
+ * moduli of step k set, r = f - K(E_k) u_prev (zero on clamped dofs) is the
+ * residual the warm start leaves, and e = u - u_prev the correction that
+ * the solve u of step k applied to it.  Full-length nodal vectors; r and e
+ * must not alias u_prev, u or each other (f may alias nothing written).
+ * Requires moduli. */
+int edd_cnn_training_pair(edd_problem *p, const double *f_dev,
+                          const double *u_prev_dev, const double *u_dev,
+                          double *r_dev, double *e_dev);
 
 /* Sizes of the problem. */
 int edd_get_info(edd_problem *p, edd_info *info);

@@ -1026,6 +1026,22 @@ int edd_cnn_loss_grad(edd_problem *p, const double *E_dev, const double *r_dev,
   return cnn_loss_grad(p, E_dev, r_dev, e_dev, grad_dev, loss);
 }
 
+int edd_cnn_training_pair(edd_problem *p, const double *f_dev, const double *u_prev_dev,
+                          const double *u_dev, double *r_dev, double *e_dev) {
+  if (!p || !f_dev || !u_prev_dev || !u_dev || !r_dev || !e_dev) return EDD_EINVAL;
+  if (!p->have_moduli) return EDD_ESTATE;
+  if (r_dev == u_prev_dev || e_dev == u_prev_dev || e_dev == u_dev || r_dev == e_dev)
+    return EDD_EINVAL;
+  // r = f - K u_prev, zero on clamped dofs
+  launch_apply_full(p, u_prev_dev, r_dev);
+  launch_axpby(p, p->ndof, 1.0, f_dev, -1.0, r_dev);
+  launch_mask_dirichlet(p, r_dev);
+  // e = u - u_prev
+  launch_copy(p, p->ndof, u_dev, e_dev);
+  launch_axpby(p, p->ndof, -1.0, u_prev_dev, 1.0, e_dev);
+  return check_hip(p, hipGetLastError());
+}
+
 int edd_cnn_train_step(edd_problem *p, const double *E_dev, const double *r_dev,
                        const double *e_dev, double lr, double *loss) {
   if (!p || !r_dev || !e_dev || !loss || !(lr > 0.0)) return EDD_EINVAL;

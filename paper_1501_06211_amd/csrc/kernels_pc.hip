@@ -776,13 +776,16 @@ __global__ void k_lanczos_coef(double *__restrict__ scal, int k, int D, double p
 // Host: geometry of the skeleton
 // --------------------------------------------------------------------------
 
-// Dense SPD inverse by Cholesky (m <= kMaxFace); returns false if not SPD.
+// Dense SPD inverse by Cholesky (m <= kMaxFace); returns false if a pivot
+// is not positive or has lost all but 1e-10 of its diagonal entry (a
+// semidefinite block, whose last pivot is rounding noise).
 static bool spd_inverse(int m, std::vector<double> &A) {
   std::vector<double> L(A);
   for (int j = 0; j < m; ++j) {
     double d = L[j * m + j];
+    const double diag = d;
     for (int k = 0; k < j; ++k) d -= L[j * m + k] * L[j * m + k];
-    if (!(d > 0.0)) return false;
+    if (!(d > 1e-10 * diag)) return false;
     d = std::sqrt(d);
     L[j * m + j] = d;
     for (int i = j + 1; i < m; ++i) {
@@ -1021,7 +1024,17 @@ int precond_setup(edd_problem *p) {
       if (class_mat[c] == A) { cls = c; break; }
     if (cls < 0) {
       std::vector<double> inv(A);
-      if (!spd_inverse(m, inv)) return EDD_EINVAL;
+      if (!spd_inverse(m, inv)) {
+        // a face with no cross point and no clamped neighbour (a skeleton
+        // that does not meet the clamp): its block of L is the singular
+        // Neumann Laplacian, so this face is preconditioned by the inverse
+        // diagonal instead
+        std::fill(inv.begin(), inv.end(), 0.0);
+        for (int i = 0; i < m; ++i) {
+          if (!(A[(size_t)i * m + i] > 0.0)) return EDD_EINVAL;
+          inv[(size_t)i * m + i] = 1.0 / A[(size_t)i * m + i];
+        }
+      }
       cls = (int)class_mat.size();
       class_mat.push_back(A);
       class_inv.push_back(std::move(inv));

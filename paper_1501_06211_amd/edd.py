@@ -7,6 +7,7 @@ Loading fails loudly when the library has not been built.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -34,7 +35,7 @@ EXPORTS = [
     "edd_apply_skeleton_op", "edd_cnn_setup", "edd_cnn_num_params",
     "edd_cnn_set_params", "edd_cnn_get_params", "edd_cnn_predict",
     "edd_cnn_loss_grad", "edd_cnn_train_step", "edd_solve_batch", "edd_autotune",
-    "edd_set_solve_variants", "edd_apply_S_noalloc",
+    "edd_set_solve_variants", "edd_apply_S_noalloc", "edd_cnn_training_pair",
 ]
 NOALLOC_MAX_INTERIOR_DOFS = 1 << 21
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
@@ -178,6 +179,7 @@ def lib():
     L.edd_cnn_predict.argtypes = [vp, vp, vp, vp]
     L.edd_cnn_loss_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
     L.edd_cnn_train_step.argtypes = [vp, vp, vp, vp, dbl, ctypes.POINTER(dbl)]
+    L.edd_cnn_training_pair.argtypes = [vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("edd_default_opts", "edd_strerror"):
@@ -196,9 +198,17 @@ def default_opts(**kw) -> SolveOpts:
     return o
 
 
-def _ptr(t: torch.Tensor, dtype=torch.float64):
-    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
-        raise ValueError(f"expected a contiguous CUDA {dtype} tensor")
+def _ptr(t, dtype=torch.float64, n=None, device=None, what="tensor"):
+    """Device address of a contiguous CUDA tensor after checking its dtype,
+    its length (``n`` entries) and its device, so that no library call ever
+    sees a buffer shorter than the kernels index."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype \
+            or not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous CUDA {dtype} tensor")
+    if n is not None and t.numel() != int(n):
+        raise ValueError(f"{what}: expected {int(n)} entries, got {t.numel()}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what}: tensor on cuda:{t.device.index}, problem on cuda:{device}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -280,19 +290,51 @@ class Problem:
             raise EddError(rc, what)
         return rc
 
+    # ---- argument checks and stream ordering ----------------------------------
+    def _v(self, t, n, what, dtype=torch.float64):
+        return _ptr(t, dtype, n=n, device=self.device, what=what)
+
+    @contextlib.contextmanager
+    def _ordered(self, *tensors):
+        """The library runs on the handle's stream.  When that is not torch's
+        current stream, the handle's stream first waits for the work already
+        queued on the current one (inputs), and the current stream then waits
+        for the library's work (outputs); the tensors are marked as used on
+        the handle's stream so the caching allocator does not recycle them
+        early."""
+        cur = torch.cuda.current_stream(self.device)
+        other = cur != self.stream
+        if other:
+            self.stream.wait_stream(cur)
+        try:
+            yield
+        finally:
+            if other:
+                cur.wait_stream(self.stream)
+                for t in tensors:
+                    if t is not None:
+                        t.record_stream(self.stream)
+
+    @property
+    def n_gamma_dofs(self):
+        return self.n_gamma * self.dim
+
     def set_element_moduli(self, E: torch.Tensor):
         dt = {torch.float64: F64, torch.float32: F32}.get(E.dtype)
         if dt is None:
             raise ValueError("moduli must be float64 or float32")
-        _ptr(E, E.dtype)
+        pe = self._v(E, self.info["n_el"], "E", E.dtype)
         self._E = E
-        self._check(lib().edd_set_element_moduli(self.h, ctypes.c_void_p(E.data_ptr()), dt),
-                    "edd_set_element_moduli")
+        with self._ordered(E):
+            self._check(lib().edd_set_element_moduli(self.h, pe, dt),
+                        "edd_set_element_moduli")
 
     def apply_K(self, u: torch.Tensor, out: torch.Tensor | None = None):
         if out is None:
             out = torch.empty_like(u)
-        self._check(lib().edd_apply_K(self.h, _ptr(u), _ptr(out)), "edd_apply_K")
+        pu, po = self._v(u, self.ndof, "u"), self._v(out, self.ndof, "out")
+        with self._ordered(u, out):
+            self._check(lib().edd_apply_K(self.h, pu, po), "edd_apply_K")
         return out
 
     def solve(self, f: torch.Tensor, u: torch.Tensor | None = None, **opts):
@@ -301,15 +343,17 @@ class Problem:
             opts.setdefault("use_initial_guess", 0)
         o = default_opts(**opts)
         st = SolveStats()
-        rc = lib().edd_solve_interface(self.h, _ptr(f), _ptr(u), ctypes.byref(o),
-                                       ctypes.byref(st))
+        pf, pu = self._v(f, self.ndof, "f"), self._v(u, self.ndof, "u")
+        with self._ordered(f, u):
+            rc = lib().edd_solve_interface(self.h, pf, pu, ctypes.byref(o), ctypes.byref(st))
         self._check(rc, "edd_solve_interface")
         return u, st.as_dict()
 
     # ---- tile shapes -----------------------------------------------------------
     def autotune(self, force=False):
         v = (ctypes.c_int * 2)()
-        self._check(lib().edd_autotune(self.h, int(force), v), "edd_autotune")
+        with self._ordered():
+            self._check(lib().edd_autotune(self.h, int(force), v), "edd_autotune")
         return int(v[0]), int(v[1])
 
     def set_solve_variants(self, f64, f32):
@@ -317,80 +361,117 @@ class Problem:
         self._check(lib().edd_set_solve_variants(self.h, v), "edd_set_solve_variants")
 
     # ---- correction network -------------------------------------------------
-    def cnn_setup(self, width=32):
-        self._check(lib().edd_cnn_setup(self.h, width), "edd_cnn_setup")
+    def _nparams(self):
         n = ctypes.c_int64()
         self._check(lib().edd_cnn_num_params(self.h, ctypes.byref(n)), "edd_cnn_num_params")
         return int(n.value)
 
+    def cnn_setup(self, width=32):
+        with self._ordered():
+            self._check(lib().edd_cnn_setup(self.h, width), "edd_cnn_setup")
+        return self._nparams()
+
     def cnn_set_params(self, params: torch.Tensor):
-        self._check(lib().edd_cnn_set_params(self.h, _ptr(params, torch.float32)),
-                    "edd_cnn_set_params")
+        pp = self._v(params, self._nparams(), "params", torch.float32)
+        with self._ordered(params):
+            self._check(lib().edd_cnn_set_params(self.h, pp), "edd_cnn_set_params")
 
     def cnn_get_params(self):
-        n = ctypes.c_int64()
-        self._check(lib().edd_cnn_num_params(self.h, ctypes.byref(n)), "edd_cnn_num_params")
-        out = torch.empty(int(n.value), dtype=torch.float32, device=self.device)
-        self._check(lib().edd_cnn_get_params(self.h, _ptr(out, torch.float32)),
-                    "edd_cnn_get_params")
+        out = torch.empty(self._nparams(), dtype=torch.float32, device=self.device)
+        with self._ordered(out):
+            self._check(lib().edd_cnn_get_params(self.h, _ptr(out, torch.float32)),
+                        "edd_cnn_get_params")
         return out
 
-    @staticmethod
-    def _optr(E):
-        return None if E is None else _ptr(E)
+    def _optr(self, E):
+        return None if E is None else self._v(E, self.info["n_el"], "E")
 
     def cnn_predict(self, r, out=None, E=None):
         if out is None:
             out = torch.empty_like(r)
-        self._check(lib().edd_cnn_predict(self.h, self._optr(E), _ptr(r), _ptr(out)),
-                    "edd_cnn_predict")
+        pe, pr, po = self._optr(E), self._v(r, self.ndof, "r"), self._v(out, self.ndof, "out")
+        with self._ordered(E, r, out):
+            self._check(lib().edd_cnn_predict(self.h, pe, pr, po), "edd_cnn_predict")
         return out
 
     def cnn_loss_grad(self, r, e, E=None):
-        n = ctypes.c_int64()
-        self._check(lib().edd_cnn_num_params(self.h, ctypes.byref(n)), "edd_cnn_num_params")
-        g = torch.empty(int(n.value), dtype=torch.float32, device=self.device)
+        g = torch.empty(self._nparams(), dtype=torch.float32, device=self.device)
         loss = ctypes.c_double()
-        self._check(lib().edd_cnn_loss_grad(self.h, self._optr(E), _ptr(r), _ptr(e),
-                                            _ptr(g, torch.float32), ctypes.byref(loss)),
-                    "edd_cnn_loss_grad")
+        pe, pr, pq = self._optr(E), self._v(r, self.ndof, "r"), self._v(e, self.ndof, "e")
+        with self._ordered(E, r, e, g):
+            self._check(lib().edd_cnn_loss_grad(self.h, pe, pr, pq, _ptr(g, torch.float32),
+                                                ctypes.byref(loss)), "edd_cnn_loss_grad")
         return float(loss.value), g
 
     def cnn_train_step(self, r, e, lr=1e-3, E=None):
         loss = ctypes.c_double()
-        self._check(lib().edd_cnn_train_step(self.h, self._optr(E), _ptr(r), _ptr(e), lr,
-                                             ctypes.byref(loss)), "edd_cnn_train_step")
+        pe, pr, pq = self._optr(E), self._v(r, self.ndof, "r"), self._v(e, self.ndof, "e")
+        with self._ordered(E, r, e):
+            self._check(lib().edd_cnn_train_step(self.h, pe, pr, pq, lr, ctypes.byref(loss)),
+                        "edd_cnn_train_step")
         return float(loss.value)
+
+    def cnn_training_pair(self, f, u_prev, u):
+        """(r, e) = (f - K u_prev, u - u_prev) for the moduli set last
+        (edd_cnn_training_pair)."""
+        r, e = torch.empty_like(f), torch.empty_like(f)
+        n = self.ndof
+        args = [self._v(t, n, nm) for t, nm in ((f, "f"), (u_prev, "u_prev"), (u, "u"),
+                                                  (r, "r"), (e, "e"))]
+        with self._ordered(f, u_prev, u, r, e):
+            self._check(lib().edd_cnn_training_pair(self.h, *args), "edd_cnn_training_pair")
+        return r, e
 
     def solve_interior(self, b, out=None, precision=F64):
         if out is None:
             out = torch.empty_like(b)
-        self._check(lib().edd_solve_interior(self.h, _ptr(b), _ptr(out), precision),
-                    "edd_solve_interior")
+        n = self.n_interior_dofs
+        pb, po = self._v(b, n, "b"), self._v(out, n, "out")
+        with self._ordered(b, out):
+            self._check(lib().edd_solve_interior(self.h, pb, po, precision),
+                        "edd_solve_interior")
         return out
 
     def apply_S(self, v, out=None, precision=F64):
         if out is None:
             out = torch.empty_like(v)
-        self._check(lib().edd_apply_S(self.h, _ptr(v), _ptr(out), precision),
-                    "edd_apply_S")
+        n = self.n_gamma_dofs
+        pv, po = self._v(v, n, "v"), self._v(out, n, "out")
+        with self._ordered(v, out):
+            self._check(lib().edd_apply_S(self.h, pv, po, precision), "edd_apply_S")
+        return out
+
+    def apply_S_noalloc(self, v, out, precision=F64):
+        """edd_apply_S_noalloc: S v with the library's static work array (the
+        output buffer is supplied by the caller)."""
+        n = self.n_gamma_dofs
+        pv, po = self._v(v, n, "v"), self._v(out, n, "out")
+        with self._ordered(v, out):
+            self._check(lib().edd_apply_S_noalloc(self.h, pv, po, precision),
+                        "edd_apply_S_noalloc")
         return out
 
     def apply_precond(self, r, out=None, **opts):
         if out is None:
             out = torch.empty_like(r)
         o = default_opts(**opts)
-        self._check(lib().edd_apply_precond(self.h, _ptr(r), _ptr(out), ctypes.byref(o)),
-                    "edd_apply_precond")
+        n = self.n_gamma_dofs
+        pr, po = self._v(r, n, "r"), self._v(out, n, "out")
+        with self._ordered(r, out):
+            self._check(lib().edd_apply_precond(self.h, pr, po, ctypes.byref(o)),
+                        "edd_apply_precond")
         return out
 
     def skeleton_op(self, which, x, weighting=1, tol=1e-12, maxit=1000, out=None):
         """which: 0 L, 1 M (lumped), 2 face-block preconditioner, 3 PCG solve."""
         if out is None:
             out = torch.empty_like(x)
-        self._check(lib().edd_apply_skeleton_op(self.h, int(which), int(weighting), _ptr(x),
-                                                _ptr(out), float(tol), int(maxit)),
-                    "edd_apply_skeleton_op")
+        n = self.n_gamma_dofs
+        px, po = self._v(x, n, "x"), self._v(out, n, "out")
+        with self._ordered(x, out):
+            self._check(lib().edd_apply_skeleton_op(self.h, int(which), int(weighting), px, po,
+                                                    float(tol), int(maxit)),
+                        "edd_apply_skeleton_op")
         return out
 
     def gamma_nodes(self):
@@ -430,11 +511,19 @@ class Problem:
 
 def solve_batch(problems, fs, us, nthreads=0, **opts):
     """Solve independent problems concurrently (edd_solve_batch).  Returns
-    (status, [stats dict per problem])."""
+    (status, [stats dict per problem]).  Each handle's stream first waits for
+    the work queued on torch's current stream; the library synchronises every
+    handle before returning."""
     n = len(problems)
+    if len(fs) != n or len(us) != n:
+        raise ValueError("solve_batch: one f and one u per problem")
     hs = (ctypes.c_void_p * n)(*[p.h.value for p in problems])
-    fp = (ctypes.c_void_p * n)(*[_ptr(f).value for f in fs])
-    up = (ctypes.c_void_p * n)(*[_ptr(u).value for u in us])
+    fp = (ctypes.c_void_p * n)(*[p._v(f, p.ndof, "f").value for p, f in zip(problems, fs)])
+    up = (ctypes.c_void_p * n)(*[p._v(u, p.ndof, "u").value for p, u in zip(problems, us)])
+    for p in problems:
+        cur = torch.cuda.current_stream(p.device)
+        if cur != p.stream:
+            p.stream.wait_stream(cur)
     o = default_opts(**opts)
     st = (SolveStats * n)()
     rc = lib().edd_solve_batch(hs, n, fp, up, ctypes.byref(o), st, int(nthreads))

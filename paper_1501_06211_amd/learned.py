@@ -45,23 +45,24 @@ def unflatten_params(flat, dim, width=32):
 def warm_start_solves(prob, f, moduli, learned=False, keep_pairs=True, log=None, **opts):
     """Solve the sequence, each step from the previous solution.
 
-    Returns a list of dicts with the solve statistics and, when keep_pairs,
-    the training pair (E, r, e) on the device."""
+    Returns (records, u_last): a list of dicts with the solve statistics and,
+    when keep_pairs, the training pair (E, r, e) on the device (formed by
+    edd_cnn_training_pair), and the solution of the last step."""
     u_prev = torch.zeros_like(f)
     out = []
     for k, E in enumerate(moduli):
         prob.set_element_moduli(E)
-        r = f - prob.apply_K(u_prev)
         u, st = prob.solve(f, u_prev.clone(), use_initial_guess=1,
                            learned_guess=1 if learned else 0, **opts)
         rec = {"stats": st}
         if log is not None:
             log(f"solve {k}: {st['iterations']} iterations, {st['t_total_ms']:.0f} ms")
         if keep_pairs:
-            rec.update(E=E.clone(), r=r, e=u - u_prev)
+            r, e = prob.cnn_training_pair(f, u_prev, u)
+            rec.update(E=E.clone(), r=r, e=e)
         out.append(rec)
         u_prev = u
-    return out
+    return out, u_prev
 
 
 def train(prob, pairs, epochs=20, lr=1e-3, seed=0, log=None):

@@ -139,10 +139,9 @@ def test_trained_network_gain_on_a_sequence():
     f = torch.tensor(p.f, device="cuda")
     prob.cnn_setup(32)
     init = learned.flatten_params(w.cnn_initial_weights(dim, 1 + dim, 32, dim, seed=1))
-    tr = learned.warm_start_solves(prob, f, seq[:ntrain])
+    tr, u_start = learned.warm_start_solves(prob, f, seq[:ntrain])
     gam = torch.tensor(prob.gamma_nodes(), device="cuda", dtype=torch.long)
     gidx = (gam[:, None] * dim + torch.arange(dim, device="cuda")).reshape(-1)
-    u_start = sum(r["e"] for r in tr)
 
     def held_out(params):
         prob.cnn_set_params(params)
