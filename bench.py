@@ -76,13 +76,22 @@ def parse():
                          "first solves, held-out solves timed plain vs learned")
     ap.add_argument("--train", type=int, default=40, help="sequence: training solves")
     ap.add_argument("--test", type=int, default=20, help="sequence: held-out solves")
-    ap.add_argument("--epochs", type=int, default=20, help="sequence: training epochs")
+    ap.add_argument("--epochs", type=int, default=20, help="network training epochs")
     ap.add_argument("--precond", default="htheta", choices=["identity", "htheta"])
-    ap.add_argument("--headline", default="plain",
-                    choices=["plain", "mixed", "relaxed"])
-    ap.add_argument("--switch", type=float, default=0.1,
-                    help="relaxed path: relative interface residual at which the "
+    ap.add_argument("--headline", default="plain", choices=list(LEG_OPTS),
+                    help="the leg whose time is the line's value")
+    ap.add_argument("--legs", default="plain,mixed,learned,learned_mixed",
+                    help="comma-separated legs timed on the same workload: plain (FP64), "
+                         "mixed (FP64 FCG whose S applies move to FP32 interior factors "
+                         "once the interface residual has dropped by --switch), learned "
+                         "(FP64 with the network's line-searched initial guess), "
+                         "learned_mixed (both)")
+    ap.add_argument("--switch", type=float, default=1e-3,
+                    help="mixed legs: relative interface residual at which the "
                          "S applies move to FP32 factors")
+    ap.add_argument("--train-fields", type=int, default=8,
+                    help="learned legs: cold solves of other cfg3-shaped moduli fields "
+                         "that train the network before the timed steps")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--graphs", type=int, default=0,
                     help="1: replay the preconditioner apply from a captured HIP graph")
@@ -90,8 +99,6 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (5 launches) whose "
                          "known byte count calibrates HBM traffic counters")
-    ap.add_argument("--no-plain", action="store_true",
-                    help="skip timing the plain FP64 path when it is not the headline")
     return ap.parse_args()
 
 
@@ -167,8 +174,21 @@ def sub_problem(w, sid):
     return sub
 
 
-def cpu_baseline(w, iterations, nsample=40):
-    """Oracle timings on a sample, scaled to one whole solve."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, iterations, ref_meta=None, nsample=40):
+    """The oracle timed on this host's cores on a bounded sample, scaled to
+    one whole solve (a model, labelled as such), plus the oracle's full
+    reference run of the same workload where one is stored."""
     import numpy as np
     import scipy.sparse.linalg as spla
     from threadpoolctl import threadpool_limits
@@ -198,17 +218,37 @@ def cpu_baseline(w, iterations, nsample=40):
     # element sweeps; plus the factorisations, condensation and back-substitution
     total_s = scale * t_fac + (iterations + 2) * (scale * t_sol) + (iterations + 1) * 2 * t_apply
     sample_s = t_fac + t_sol + t_apply
-    return {
+    out = {
         "value": total_s * 1e3,
         "unit": "ms",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"{nsample} of {nsub} subdomains: oracle assembly + SuperLU factor "
-                   f"and one solve each ({t_fac + t_sol:.1f} s), one element-by-element "
-                   f"K apply of the full mesh ({t_apply:.2f} s); scaled x{scale:.0f} "
-                   f"over subdomains and by {iterations} interface iterations "
-                   f"(sample took {sample_s:.1f} s, 1 thread)"),
+        "modelled": True,
+        "sample": (f"MODELLED from a timed sample: {nsample} of {nsub} subdomains "
+                   f"(oracle assembly + SuperLU factor and one solve each, "
+                   f"{t_fac + t_sol:.1f} s) and one element-by-element K apply of the full "
+                   f"mesh ({t_apply:.2f} s), scaled x{scale:.0f} over subdomains and by "
+                   f"{iterations} interface iterations; the sample took {sample_s:.1f} s "
+                   f"on 1 thread"),
+        "host": {"os_cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+                 "threads_used": 1},
     }
+    if ref_meta is not None:
+        first = ref_meta["rounds"][0]
+        out["full_oracle_run"] = {
+            "what": "measured, not modelled: the oracle's FP64 Schur route on the whole "
+                    "workload (per-subdomain sparse LU, flexible CG with inverse-Lanczos "
+                    "Hhat_0.5), refined in long double to the stored reference",
+            "first_solve_seconds": round(first["seconds"], 1),
+            "first_solve_iterations": first["iterations"],
+            "first_solve_rel_residual": ref_meta["rounds"][1]["rel_residual"],
+            "total_seconds": ref_meta["wall_seconds"],
+            "worker_processes": ref_meta["worker_processes"],
+            "host_cpu_count": ref_meta["os_cpu_count"],
+            "host_cpu_model": ref_meta["cpu_model"],
+            "host": "the build container, not this host",
+        }
+    return out
 
 
 def run_batch(args):
@@ -296,7 +336,7 @@ def run_sequence(args):
         workloads.cnn_initial_weights(3, 4, 32, 3, seed=1)))
     opts = dict(tol=args.tol, maxit=5000)
     t0 = time.perf_counter()
-    tr = learned.warm_start_solves(
+    tr, u_prev = learned.warm_start_solves(
         prob, f, seq[:args.train],
         log=lambda s: print("[bench]   training " + s, file=sys.stderr, flush=True), **opts)
     print(f"[bench] {args.train} training solves in {time.perf_counter() - t0:.1f} s",
@@ -307,7 +347,6 @@ def run_sequence(args):
                          log=lambda s: print("[bench]   " + s, file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    u_prev = sum(r["e"] for r in tr)
     del tr
     rows = []
     for k, E in enumerate(seq[args.train:]):
@@ -353,30 +392,104 @@ def run_sequence(args):
     print(json.dumps(out))
 
 
+LEG_OPTS = {
+    # leg: (factor precisions, extra solve options)
+    "plain": ("f64", {}),
+    "mixed": ("f64+f32", {"mixed": True}),
+    "learned": ("f64", {"learned_guess": 1}),
+    "learned_mixed": ("f64+f32", {"mixed": True, "learned_guess": 1}),
+}
+
+
+def leg_opts(leg, args):
+    from paper_1501_06211_amd import edd
+    _, extra = LEG_OPTS[leg]
+    o = solve_opts("relaxed" if extra.get("mixed") else "plain", args.precond, args.tol,
+                   args.switch, args.graphs)
+    if extra.get("learned_guess"):
+        o["learned_guess"] = 1
+    return o
+
+
+def reference_solution(w):
+    """The stored oracle reference for this workload, if there is one."""
+    import numpy as np
+    base = os.path.join(ROOT, "tests", "golden", f"{w.name}_u_ref")
+    if not (os.path.exists(base + ".npy") and os.path.exists(base + ".json")):
+        return None, None
+    with open(base + ".json") as fh:
+        meta = json.load(fh)
+    return np.load(base + ".npy"), meta
+
+
+def train_network(prob, args, log):
+    """Train the correction network outside the timed region on cold solves
+    of cfg3-shaped moduli fields that are not the timed field: pairs
+    (E_k, r = f, e = u_k) formed by the library.  Returns the statistics."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1501_06211_amd import learned
+    w0 = make_workload(args.workload)
+    t0 = time.perf_counter()
+    fields = [torch.tensor(E, device="cuda")
+              for E in workloads.simp_sequence_3d(args.train_fields, *w0.nel)]
+    t_gen = time.perf_counter() - t0
+    f = torch.tensor(w0.f, device="cuda")
+    prob.cnn_setup(32)
+    prob.cnn_set_params(learned.flatten_params(
+        workloads.cnn_initial_weights(w0.dim, 1 + w0.dim, 32, w0.dim, seed=1)))
+    zero = torch.zeros_like(f)
+    pairs, its = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, E in enumerate(fields):
+        prob.set_element_moduli(E)
+        u, st = prob.solve(f, **solve_opts("plain", args.precond, args.tol, args.switch))
+        r, e = prob.cnn_training_pair(f, zero, u)
+        pairs.append({"E": E, "r": r, "e": e})
+        its.append(st["iterations"])
+    torch.cuda.synchronize()
+    t_solves = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = learned.train(prob, pairs, epochs=args.epochs, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"network: {len(fields)} training solves in {t_solves:.1f} s, {args.epochs} epochs "
+        f"in {t_train:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    return {"fields": len(fields), "field_kind": "simp_sequence_3d (seeds 7000+k), "
+            "not the timed field", "pairs": "cold solves: r = f, e = u_k",
+            "solve_iterations": its, "seconds_generate_fields": round(t_gen, 2),
+            "seconds_solves": round(t_solves, 2), "epochs": args.epochs,
+            "seconds_train": round(t_train, 2), "loss_first_epoch": round(hist[0], 4),
+            "loss_last_epoch": round(hist[-1], 4)}
+
+
+def one_gpu_guard(args):
+    if args.gpus != 1:
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
+                                   "(no multi-GPU path is built)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+
 def main():
     args = parse()
+    one_gpu_guard(args)
     if args.workload == "sequence":
-        if args.gpus != 1:
-            print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
-                              "n_gpus": args.gpus}))
-            sys.exit(2)
         run_sequence(args)
         return
     if args.workload == "batch":
-        if args.gpus != 1:
-            print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
-                              "n_gpus": args.gpus}))
-            sys.exit(2)
         run_batch(args)
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
     import numpy as np
     import torch
 
     from paper_1501_06211_amd import edd
+
+    def log(s):
+        print(f"[bench] {s}", file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -386,53 +499,58 @@ def main():
             torch.mul(src, 1.0, out=dst)  # one elementwise kernel: 1 GiB in, 1 GiB out
         torch.cuda.synchronize()
         del src, dst
-        print("[bench] copy calibration: 5 x 1 GiB device copies done",
-              file=sys.stderr, flush=True)
+        log("copy calibration: 5 x 1 GiB device copies done")
     w = make_workload(args.workload)
     E = torch.tensor(w.E, device="cuda")
     f = torch.tensor(w.f, device="cuda")
-    u = torch.zeros_like(f)
-
-    head = args.headline
-    res = {}
-    other = "relaxed" if head == "plain" else "plain"
-    paths = [head] if args.no_plain else [head, other]
-    for path in paths:
-        # each path sets up only the factor precisions it uses: the plain
-        # path FP64, the mixed paths FP64 and FP32
-        prec = edd.F64 if path == "plain" else edd.F64 | edd.F32
+    legs = [l for l in args.legs.split(",") if l]
+    if w.dim != 3:
+        legs = [l for l in legs if not l.startswith("learned")]
+    head = args.headline if args.headline in legs else legs[0]
+    res, training, info, variants = {}, None, None, None
+    params = None
+    # one handle per factor-precision set: each path builds only the factors it uses
+    for prec_name in ("f64", "f64+f32"):
+        group = [l for l in legs if LEG_OPTS[l][0] == prec_name]
+        if not group:
+            continue
+        prec = edd.F64 if prec_name == "f64" else edd.F64 | edd.F32
         prob = edd.Problem.from_workload(w, factor_precision=prec)
-        # substitution variants: timed once per shape class, outside the
-        # timed region (the choice is cached for later handles)
         prob.set_element_moduli(E)
-        pv = prob.autotune()
-        print(f"[bench] {path}: autotuned substitution variants (FP64, FP32): {pv}",
-              file=sys.stderr, flush=True)
-        ms, stats, kt = time_path(prob, E, f, u,
-                                  solve_opts(path, args.precond, args.tol, args.switch, args.graphs),
-                                  args.steps, args.warmup, timing=True)
-        res[path] = (ms, stats, kt)
-        if path == head:
+        pv = prob.autotune()  # timed once per shape class, outside the timed region
+        log(f"{prec_name}: autotuned substitution variants (FP64, FP32): {pv}")
+        if info is None:
             info, variants = prob.info, pv
+        for leg in group:
+            if leg.startswith("learned"):
+                if params is None:
+                    training = train_network(prob, args, log)
+                    params = prob.cnn_get_params()
+                else:
+                    prob.cnn_setup(32)
+                    prob.cnn_set_params(params)
+            u = torch.zeros_like(f)
+            ms, stats, kt = time_path(prob, E, f, u, leg_opts(leg, args), args.steps,
+                                      args.warmup, timing=True)
+            res[leg] = {"ms": ms, "stats": stats, "kt": kt, "u": u.cpu().numpy()}
+            log(f"{leg}: {ms:.1f} ms/step, its={stats[-1]['iterations']} "
+                f"res={stats[-1]['rel_residual']:.2e} flags={stats[-1]['flags']}")
         prob.close()
-        print(f"[bench] {path}: {ms:.1f} ms/step, its={stats[-1]['iterations']} "
-              f"outer={stats[-1]['outer_iterations']} res={stats[-1]['rel_residual']:.2e}",
-              file=sys.stderr, flush=True)
-    ms, stats, kt = res[head]
+        del prob
+
+    ms, stats, kt = res[head]["ms"], res[head]["stats"], res[head]["kt"]
     st = stats[-1]
     if st["rel_residual"] > args.tol:
-        print(f"[bench] WARNING: residual {st['rel_residual']:.2e} above {args.tol}",
-              file=sys.stderr)
+        log(f"WARNING: residual {st['rel_residual']:.2e} above {args.tol}")
 
-    # roofline of the batched substitution kernel (the dominant byte stream):
-    # both triangular sweeps read every band entry once, plus the right-hand
-    # side in and the solution out, FP64
-    def band_roof(name, word):
+    # roofline of the batched interior solve (the dominant byte stream): both
+    # triangular sweeps read every band entry once, the dissection couplings
+    # twice (separator right-hand side and tail update), right-hand side in
+    # and solution out
+    def band_roof(kt, name, word):
         n_solve, t_solve = kt[name]
         if not n_solve:
             return None
-        # the dissection couplings are read twice (separator right-hand
-        # side and tail update)
         bytes_per_launch = (2 * info["factor_entries"] * word
                             + 2 * info["coupling_entries"] * word
                             + 16 * info["n_interior_dofs"])
@@ -445,9 +563,34 @@ def main():
                 "kernel": kname,
                 "avg_launch_ms": round(avg_ms, 4), "launches": n_solve,
                 "total_ms": round(t_solve, 2), "bytes_per_launch": bytes_per_launch}
-    roofs = [r for r in (band_roof("band_solve", 8), band_roof("band_solve32", 4)) if r]
-    roofs.sort(key=lambda r: -r["total_ms"])
-    roof = roofs[0]
+    roof = band_roof(kt, "band_solve", 8)
+
+    u_ref, ref_meta = reference_solution(w)
+    u_plain = res["plain"]["u"] if "plain" in res else None
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    leg_out = {}
+    for leg, r in res.items():
+        s = r["stats"][-1]
+        d = {"ms_per_step": round(r["ms"], 3), "iterations": s["iterations"],
+             "rel_residual": s["rel_residual"], "compliance": s["compliance"],
+             "flags": s["flags"], "factors": LEG_OPTS[leg][0]}
+        if LEG_OPTS[leg][1].get("mixed"):
+            d["fp32_switch_rel_residual"] = args.switch
+        if LEG_OPTS[leg][1].get("learned_guess"):
+            d["learned_alpha"] = s["learned_alpha"]
+        if u_plain is not None:
+            d["u_err_vs_plain_f64"] = rel(r["u"], u_plain)
+            d["compliance_err_vs_plain_f64"] = abs(s["compliance"] - res["plain"]["stats"][-1]
+                                                   ["compliance"]) / abs(s["compliance"])
+            d["speedup_vs_plain"] = round(res["plain"]["ms"] / r["ms"], 3)
+        if u_ref is not None:
+            d["u_err_vs_reference"] = rel(r["u"], u_ref)
+            d["compliance_err_vs_reference"] = abs(s["compliance"] - ref_meta["compliance"]) \
+                / abs(ref_meta["compliance"])
+        leg_out[leg] = d
 
     out = {
         "metric": "time to rel.res 1e-8, 3D 1.6M dofs: plain vs learned+mixed; HBM GB/s frac",
@@ -460,7 +603,7 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64" if head == "plain" else "f64+f32",
+        "dtype": "f64" if LEG_OPTS[head][0] == "f64" else "f64+f32",
         "data": "synthetic",
         "layout": {"band_blocks": info["band_blocks"], "band_entries": info["factor_entries"],
                    "coupling_entries": info["coupling_entries"],
@@ -468,26 +611,28 @@ def main():
                    "substitution_variants": list(variants)},
         "config": {"workload": w.name, "ndof": int(w.ndof), "subdomains": int(w.n_sub),
                    "path": head, "precond": args.precond, "tol": args.tol,
+                   "step": "set_element_moduli + solve from zero",
                    "parallelism": "single GPU"},
         "solve": {"iterations": st["iterations"], "outer_iterations": st["outer_iterations"],
                   "rel_residual": st["rel_residual"], "compliance": st["compliance"],
                   "flags": st["flags"]},
+        "legs": leg_out,
         "kernels_ms": {k: (round(v[1] / v[0], 4) if v[0] else None) for k, v in kt.items()},
         "roofline": roof,
     }
-    if len(roofs) > 1:
-        out["roofline_second"] = roofs[1]
-    if other in res:
-        om, ost, _ = res[other]
-        key = "plain_f64" if other == "plain" else "mixed_relaxed"
-        out[key] = {"ms_per_step": round(om, 3), "iterations": ost[-1]["iterations"],
-                    "rel_residual": ost[-1]["rel_residual"],
-                    "compliance": ost[-1]["compliance"], "flags": ost[-1]["flags"],
-                    "speedup_vs_headline": round(ms / om, 3)}
-        out["compliance_rel_diff"] = abs(st["compliance"] - ost[-1]["compliance"]) / abs(ost[-1]["compliance"])
+    if "mixed" in res:
+        r2 = band_roof(res["mixed"]["kt"], "band_solve32", 4)
+        if r2:
+            out["roofline_fp32_factors"] = r2
+    if training is not None:
+        out["training"] = training
+    if ref_meta is not None:
+        out["reference"] = {"kind": ref_meta["kind"],
+                            "rel_residual": ref_meta["rel_residual_long_double"],
+                            "file": f"tests/golden/{w.name}_u_ref.npy"}
     if not args.no_cpu_baseline:
-        its = res["plain"][1][-1]["iterations"] if "plain" in res else st["iterations"]
-        out["cpu_baseline"] = cpu_baseline(w, its) if w.dim == 3 else None
+        its = res["plain"]["stats"][-1]["iterations"] if "plain" in res else st["iterations"]
+        out["cpu_baseline"] = cpu_baseline(w, its, ref_meta) if w.dim == 3 else None
     print(json.dumps(out))
 
 

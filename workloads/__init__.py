@@ -19,6 +19,7 @@ from .gen import (  # noqa: F401
     cantilever3d_simp_128x64x64,
     to_sequence_2d,
     to_sequence_3d,
+    simp_sequence_3d,
     cnn_initial_weights,
     batch_uneven_problem,
     even_cuts,

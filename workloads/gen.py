@@ -221,6 +221,20 @@ def to_sequence_3d(nsteps=60, nx=128, ny=64, nz=64, ell=20.0, base_seed=6000,
         yield 1e-3 + _field_to_elements(rho) ** 3
 
 
+def simp_sequence_3d(nsteps, nx=128, ny=64, nz=64, ell=20.0, base_seed=7000,
+                     blend=0.1):
+    """Moduli fields shaped like the 3D SIMP cantilever's (smooth field,
+    rho = Phi(phi), E = 1e-3 + rho^3 (1 - 1e-3)), blended 10% per step toward
+    a fresh field as in ``to_sequence_3d`` but not thresholded."""
+    phi = gaussian_random_field((nx, ny, nz), ell, base_seed)
+    for k in range(nsteps):
+        if k > 0:
+            g = gaussian_random_field((nx, ny, nz), ell, base_seed + k)
+            phi = (1.0 - blend) * phi + blend * g
+            phi = (phi - phi.mean()) / phi.std()
+        yield simp_moduli(_field_to_elements(ndtr(phi)))
+
+
 def cnn_initial_weights(dim, cin, width, cout, seed, nlayers=4):
     """Seeded initial weights of the correction network: per layer a tap
     array of shape (3^dim, c_in, c_out) drawn from N(0, 2 / (3^dim c_in))
