@@ -348,6 +348,88 @@ int edd_get_info(edd_problem *p, edd_info *info);
 int edd_get_gamma_nodes(edd_problem *p, int32_t *nodes_host);
 int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host);
 
+/* ---- topology optimisation (Section 5) -----------------------------------
+ * The fixed-point loop of Section 5 for min f^T u subject to K(rho) u = f,
+ * K(rho) = sum_i E(rho_i) K0_i (eq. (NumberTen)), sum_i rho_i <= V and
+ * rho_min <= rho_i <= rho_max: finite element analysis (edd_solve_interface),
+ * an Optimality Criteria density update, a convergence check.  With
+ * penal = 1 and emin = 0, E(rho) = rho: the paper's Variable Thickness
+ * Sheet problem; otherwise E(rho) = emin + rho^penal (1 - emin).
+ * Densities are FP64 device vectors of n_el values in element order. */
+
+typedef struct edd_oc_params {
+  double volume;           /* V, the bound on sum_i rho_i                     */
+  double rho_min, rho_max; /* box bounds, 0 < rho_min <= rho_max              */
+  double move;             /* move limit |rho_new - rho| <= move              */
+  double eta;              /* damping exponent of the OC fixed point          */
+  double penal, emin;      /* E(rho) as above (penal >= 1, 0 <= emin < 1)     */
+} edd_oc_params;
+
+typedef struct edd_oc_result {
+  double lambda;     /* multiplier of the volume constraint (0: the bound was */
+                     /* not reached with every density at its upper limit;  */
+                     /* +inf: the lower limits already exceed it)           */
+  double volume;     /* sum of the new densities                              */
+  double max_change; /* max_i |rho_new_i - rho_i|                             */
+} edd_oc_result;
+
+/* s_e = u_e^T K0 u_e for every element: twice the strain energy of the
+ * element at unit modulus, -dc/dE_e (clamped dofs of u count as zero).
+ * u_dev: full nodal vector; s_dev: n_el values.  Asynchronous. */
+int edd_element_energies(edd_problem *p, const double *u_dev, double *s_dev);
+
+/* One OC update: with g_i = E'(rho_i) s_i,
+ *   rho_new_i = clamp(rho_i (g_i / Lambda)^eta, max(rho_min, rho_i - move),
+ *                     min(rho_max, rho_i + move)),
+ * Lambda found on the device so that sum_i rho_new_i = V (multisection on
+ * log Lambda to a relative width below 1e-11).  E_new_dev (may be NULL)
+ * receives E(rho_new).  rho_new_dev must not alias rho_dev or s_dev.
+ * Returns EDD_EINVAL for bad parameters.  Synchronises. */
+int edd_oc_update(edd_problem *p, const double *rho_dev, const double *s_dev,
+                  const edd_oc_params *o, double *rho_new_dev, double *E_new_dev,
+                  edd_oc_result *res);
+
+typedef struct edd_topopt_opts {
+  double volfrac;            /* V = volfrac * n_el                            */
+  double rho_min, rho_max, move, eta, penal, emin;  /* as edd_oc_params       */
+  double change_tol;         /* stop when max |rho_new - rho| <= change_tol   */
+  int maxit;                 /* fixed-point iterations at most                */
+  int adaptive_tol;          /* 1: Krylov tolerance of step k is             */
+                             /* |c_{k-1} - c_{k-2}| / c_{k-1} clamped to     */
+                             /* [tol_min, tol_max] (tol_max for the first    */
+                             /* two steps); 0: tol_min throughout            */
+  double tol_min, tol_max;
+  int warm_start;            /* 1: each analysis starts from the previous u  */
+} edd_topopt_opts;
+
+typedef struct edd_topopt_stats {
+  int status;                /* EDD_OK, or EDD_NOT_CONVERGED if an analysis  */
+                             /* missed its tolerance                         */
+  int steps;                 /* fixed-point iterations done                  */
+  int converged;             /* 1 if the change test was met                 */
+  int krylov_iterations;     /* interface iterations over all analyses       */
+  double avg_krylov;         /* per analysis                                 */
+  double compliance;         /* of the last analysis                          */
+  double max_change, volume; /* of the last update                           */
+  double t_total_ms, t_moduli_ms, t_solve_ms, t_update_ms;
+} edd_topopt_stats;
+
+/* Defaults: volfrac 0.5, rho in [1e-3, 1], move 0.2, eta 0.5, penal 1,
+ * emin 0 (Variable Thickness Sheet), change_tol 1e-2, maxit 100, adaptive
+ * tolerance in [1e-8, 1e-2], warm start. */
+void edd_default_topopt_opts(edd_topopt_opts *o);
+
+/* Run the loop from the densities in rho_dev (n_el values, overwritten by
+ * the final design); u_dev (full nodal vector) receives the last analysis.
+ * so: options of the analyses (tol and use_initial_guess are set by the
+ * loop; NULL = edd_default_opts).  st may be NULL.  history_host (NULL or
+ * 5 * maxit doubles) receives per step: compliance, Krylov tolerance,
+ * interface iterations, max density change, final relative residual.
+ * Synchronises. */
+int edd_topopt_run(edd_problem *p, const double *f_dev, double *rho_dev, double *u_dev,
+                   const edd_topopt_opts *to, const edd_solve_opts *so,
+                   edd_topopt_stats *st, double *history_host);
+
 /* ---- kernel timing ----------------------------------------------------- */
 #define EDD_KT_BAND_SOLVE 0    /* batched forward+backward substitution,   */
                                /* FP64 factors                             */

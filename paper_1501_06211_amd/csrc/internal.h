@@ -217,6 +217,10 @@ struct edd_problem {
 
   int last_hip_error = 0;
 
+  // topology optimisation work vectors (n_el each): element energies,
+  // moduli, updated densities (topopt.hip)
+  double *to_s_d = nullptr, *to_E_d = nullptr, *to_rho_d = nullptr;
+
   // address of the static work array of edd_apply_S_noalloc on this
   // handle's device (noalloc.hip)
   double *scratch_d = nullptr;
@@ -320,6 +324,11 @@ void launch_residual_norms(edd_problem *p, const double *f, const double *y,
 void apply_S_with(edd_problem *p, const double *v, double *y, int prec, double *t);
 // look up the static work array of edd_apply_S_noalloc (noalloc.hip)
 int scratch_init(edd_problem *p);
+
+// topology optimisation (topopt.hip)
+int element_energies(edd_problem *p, const double *u, double *s);
+int oc_update(edd_problem *p, const double *rho, const double *s, const edd_oc_params &o,
+              double *rho_new, double *E_new, edd_oc_result *res);
 
 // preconditioner (kernels_pc.hip)
 int precond_apply(edd_problem *p, const double *r, double *z,

@@ -36,6 +36,7 @@ EXPORTS = [
     "edd_cnn_set_params", "edd_cnn_get_params", "edd_cnn_predict",
     "edd_cnn_loss_grad", "edd_cnn_train_step", "edd_solve_batch", "edd_autotune",
     "edd_set_solve_variants", "edd_apply_S_noalloc", "edd_cnn_training_pair",
+    "edd_element_energies", "edd_oc_update", "edd_default_topopt_opts", "edd_topopt_run",
 ]
 NOALLOC_MAX_INTERIOR_DOFS = 1 << 21
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
@@ -119,6 +120,43 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class OcParams(ctypes.Structure):
+    _fields_ = [("volume", ctypes.c_double), ("rho_min", ctypes.c_double),
+                ("rho_max", ctypes.c_double), ("move", ctypes.c_double),
+                ("eta", ctypes.c_double), ("penal", ctypes.c_double),
+                ("emin", ctypes.c_double)]
+
+
+class OcResult(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("volume", ctypes.c_double),
+                ("max_change", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"lambda": self.lambda_, "volume": self.volume, "max_change": self.max_change}
+
+
+class TopoptOpts(ctypes.Structure):
+    _fields_ = [("volfrac", ctypes.c_double), ("rho_min", ctypes.c_double),
+                ("rho_max", ctypes.c_double), ("move", ctypes.c_double),
+                ("eta", ctypes.c_double), ("penal", ctypes.c_double),
+                ("emin", ctypes.c_double), ("change_tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("adaptive_tol", ctypes.c_int),
+                ("tol_min", ctypes.c_double), ("tol_max", ctypes.c_double),
+                ("warm_start", ctypes.c_int)]
+
+
+class TopoptStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("steps", ctypes.c_int),
+                ("converged", ctypes.c_int), ("krylov_iterations", ctypes.c_int),
+                ("avg_krylov", ctypes.c_double), ("compliance", ctypes.c_double),
+                ("max_change", ctypes.c_double), ("volume", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double), ("t_moduli_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("t_update_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class KernelTimes(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64 * 8), ("total_ms", ctypes.c_double * 8)]
 
@@ -180,9 +218,17 @@ def lib():
     L.edd_cnn_loss_grad.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl)]
     L.edd_cnn_train_step.argtypes = [vp, vp, vp, vp, dbl, ctypes.POINTER(dbl)]
     L.edd_cnn_training_pair.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.edd_element_energies.argtypes = [vp, vp, vp]
+    L.edd_oc_update.argtypes = [vp, vp, vp, ctypes.POINTER(OcParams), vp, vp,
+                                ctypes.POINTER(OcResult)]
+    L.edd_default_topopt_opts.argtypes = [ctypes.POINTER(TopoptOpts)]
+    L.edd_default_topopt_opts.restype = None
+    L.edd_topopt_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(TopoptOpts),
+                                 ctypes.POINTER(SolveOpts), ctypes.POINTER(TopoptStats),
+                                 ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS:
         f = getattr(L, name)
-        if name not in ("edd_default_opts", "edd_strerror"):
+        if name not in ("edd_default_opts", "edd_strerror", "edd_default_topopt_opts"):
             f.restype = i32
     _LIB = L
     return L
@@ -421,6 +467,59 @@ class Problem:
         with self._ordered(f, u_prev, u, r, e):
             self._check(lib().edd_cnn_training_pair(self.h, *args), "edd_cnn_training_pair")
         return r, e
+
+    # ---- topology optimisation (Section 5) -------------------------------------
+    def element_energies(self, u, out=None):
+        """s_e = u_e^T K0 u_e (edd_element_energies)."""
+        n_el = self.info["n_el"]
+        if out is None:
+            out = torch.empty(n_el, dtype=torch.float64, device=self.device)
+        pu, po = self._v(u, self.ndof, "u"), self._v(out, n_el, "out")
+        with self._ordered(u, out):
+            self._check(lib().edd_element_energies(self.h, pu, po), "edd_element_energies")
+        return out
+
+    def oc_update(self, rho, s, volume, rho_min=1e-3, rho_max=1.0, move=0.2, eta=0.5,
+                  penal=1.0, emin=0.0):
+        """One OC density update (edd_oc_update).  Returns (rho_new, E_new,
+        result dict)."""
+        n_el = self.info["n_el"]
+        rho_new = torch.empty(n_el, dtype=torch.float64, device=self.device)
+        E_new = torch.empty_like(rho_new)
+        prm = OcParams(volume, rho_min, rho_max, move, eta, penal, emin)
+        res = OcResult()
+        pr, ps = self._v(rho, n_el, "rho"), self._v(s, n_el, "s")
+        with self._ordered(rho, s, rho_new, E_new):
+            self._check(lib().edd_oc_update(self.h, pr, ps, ctypes.byref(prm), _ptr(rho_new),
+                                            _ptr(E_new), ctypes.byref(res)), "edd_oc_update")
+        return rho_new, E_new, res.as_dict()
+
+    def topopt(self, f, rho, u=None, solve_opts=None, **opts):
+        """The fixed-point loop of Section 5 (edd_topopt_run).  rho (n_el,
+        FP64) is overwritten by the final design.  Returns (rho, u, stats,
+        history) with history an array of rows (compliance, tolerance,
+        iterations, max change, residual) per step."""
+        import numpy as np
+        to = TopoptOpts()
+        lib().edd_default_topopt_opts(ctypes.byref(to))
+        for k, v in opts.items():
+            if not hasattr(to, k):
+                raise KeyError(f"unknown topology-optimisation option {k!r}")
+            setattr(to, k, v)
+        so = default_opts(**(solve_opts or {}))
+        if u is None:
+            u = torch.zeros_like(f)
+        st = TopoptStats()
+        hist = np.zeros(5 * to.maxit)
+        pf, pr, pu = (self._v(f, self.ndof, "f"), self._v(rho, self.info["n_el"], "rho"),
+                      self._v(u, self.ndof, "u"))
+        with self._ordered(f, rho, u):
+            rc = lib().edd_topopt_run(self.h, pf, pr, pu, ctypes.byref(to), ctypes.byref(so),
+                                      ctypes.byref(st),
+                                      hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._check(rc, "edd_topopt_run")
+        d = st.as_dict()
+        return rho, u, d, hist.reshape(-1, 5)[:d["steps"]]
 
     def solve_interior(self, b, out=None, precision=F64):
         if out is None:
