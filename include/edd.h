@@ -72,6 +72,8 @@ extern "C" {
 
 #define EDD_PC_IDENTITY 0 /* S~ = I                                           */
 #define EDD_PC_HTHETA 1   /* S~ = Hhat_theta by inverse Lanczos (Section 3)   */
+#define EDD_PC_SCHUR 2    /* S~ = S itself, applied by an inner interface     */
+                          /* solve to mixed_inner_tol (edd_solve_gmres only)  */
 
 /* stats.flags bits */
 #define EDD_FLAG_TRUE_RES_RESTART 1 /* recursive residual disagreed; restarted */
@@ -215,6 +217,22 @@ int edd_apply_K(edd_problem *p, const double *u_dev, double *y_dev);
  * the tolerance is not met within the iteration limits. */
 int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
                         const edd_solve_opts *o, edd_solve_stats *s);
+
+/* Solve K u = f on the free dofs by the paper's own Krylov method (Section
+ * 3): flexible GMRES on the whole system, preconditioned from the right by
+ * the block-triangular P~ = [K_II K_IG; 0 S~], whose inverse is applied in
+ * the factored order printed there (S~^{-1} on the interface part, then the
+ * interior part K_II^{-1} (v_I - K_IG z_G)).  S~ is o->precond: EDD_PC_IDENTITY,
+ * EDD_PC_HTHETA (settings as for edd_solve_interface) or EDD_PC_SCHUR (S
+ * itself by an inner interface solve to relative tolerance
+ * o->mixed_inner_tol; GMRES then needs at most two iterations).  Stops when
+ * the GMRES residual is <= tol ||f||, then checks the FP64 true residual and
+ * restarts from u if it misses.  o->flexible_window is the restart length
+ * (0: 256, at most 256); o->maxit bounds the GMRES iterations; stats report
+ * them in `iterations`, and the inner interface iterations of EDD_PC_SCHUR
+ * (at most 5000 per application) in `outer_iterations`.  Synchronises. */
+int edd_solve_gmres(edd_problem *p, const double *f_dev, double *u_dev,
+                    const edd_solve_opts *o, edd_solve_stats *s);
 
 /* ---- parts of the path, exposed for checking and for composition ------ */
 

@@ -47,7 +47,7 @@ enum : int {
   S_C_BASE = 16,
   S_PQ_BASE = 16 + 256,
   S_PC_BASE = 16 + 512,
-  S_TOTAL = 2048
+  S_TOTAL = kScalTotal
 };
 
 void *dev_alloc(edd_problem *p, size_t bytes) {
@@ -300,6 +300,28 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   }
   *iters = converged_at >= 0 ? converged_at : k;
   return status;
+}
+
+// S x = rhs by the interface flexible CG to ||rhs - S x|| <= rel_tol ||rhs||
+// (FP64 interior factors, zero initial guess); for composition (the full
+// GMRES path applies S~ = S with it).
+int interface_solve(edd_problem *p, const double *rhs, double *x, double rel_tol,
+                    const edd_solve_opts *o, edd_solve_stats *st, int maxit, int *iters) {
+  const int64_t nG = p->n_gamma * p->g.dim;
+  {
+    const double *a[1] = {rhs}, *b[1] = {rhs};
+    launch_dots(p, nG, 1, a, b, S_RES);
+  }
+  int rc = read_scalars(p, S_RES, 1);
+  if (rc) return rc;
+  const double nr = std::sqrt(p->scal_h[S_RES]);
+  if (!std::isfinite(nr)) return EDD_EINVAL;
+  if (nr == 0.0) {
+    launch_fill(p, nG, 0.0, x);
+    *iters = 0;
+    return EDD_OK;
+  }
+  return interface_fcg(p, rhs, x, EDD_F64, rel_tol * nr, false, o, st, maxit, 256, iters);
 }
 
 // The three steps of eq. (3MatSplit) with interior factors of precision

@@ -22,6 +22,12 @@ constexpr int kDirichlet = -1;
 // correction network: layers and hidden width
 constexpr int kCnnLayers = 4;
 constexpr int kCnnWidth = 32;
+
+// Scalar slots of p->scal_d (FP64 device scalars read back through the pinned
+// p->scal_h): the interface solver below 528 (api.hip), the preconditioner
+// 528..1499 (kernels_pc.hip), the OC update 1536..1599 (topopt.hip), the
+// network 1600..1605 (kernels_cnn.hip), full GMRES 2048..4095 (gmres.hip).
+constexpr int kScalTotal = 4096;
 __host__ __device__ inline int gamma_code(int g) { return -g - 2; }
 __host__ __device__ inline int gamma_index(int code) { return -code - 2; }
 
@@ -217,6 +223,12 @@ struct edd_problem {
 
   int last_hip_error = 0;
 
+  // full-system GMRES (gmres.hip): Arnoldi basis V ((cap+1) x ndof),
+  // preconditioned directions Z (cap x ndof), work vectors
+  int gm_cap = 0;
+  double *gm_V = nullptr, *gm_Z = nullptr, *gm_w = nullptr;
+  double *gm_vG = nullptr, *gm_zG = nullptr, *gm_tI = nullptr;
+
   // topology optimisation work vectors (n_el each): element energies,
   // moduli, updated densities (topopt.hip)
   double *to_s_d = nullptr, *to_E_d = nullptr, *to_rho_d = nullptr;
@@ -322,6 +334,9 @@ void launch_residual_norms(edd_problem *p, const double *f, const double *y,
 
 // y = S v with t (n_idofs doubles) as the interior work vector (api.hip)
 void apply_S_with(edd_problem *p, const double *v, double *y, int prec, double *t);
+// S x = rhs by the interface flexible CG to a relative tolerance (api.hip)
+int interface_solve(edd_problem *p, const double *rhs, double *x, double rel_tol,
+                    const edd_solve_opts *o, edd_solve_stats *st, int maxit, int *iters);
 // look up the static work array of edd_apply_S_noalloc (noalloc.hip)
 int scratch_init(edd_problem *p);
 

@@ -22,7 +22,7 @@ EINVAL, ENOMEM, EHIP, ESTATE, ENOTSPD, EBREAKDOWN = -1, -2, -3, -4, -5, -6
 F64, F32 = 1, 2
 CLAMP_X0, CLAMP_X1, CLAMP_Y0, CLAMP_Y1, CLAMP_Z0, CLAMP_Z1 = 1, 2, 4, 8, 16, 32
 MODE_F64, MODE_MIXED, MODE_RELAXED = 0, 1, 2
-PC_IDENTITY, PC_HTHETA = 0, 1
+PC_IDENTITY, PC_HTHETA, PC_SCHUR = 0, 1, 2
 FLAG_TRUE_RES_RESTART, FLAG_MIXED_FALLBACK, FLAG_PC_DROPPED = 1, 2, 4
 FLAG_LEARNED_REJECTED = 8
 
@@ -37,6 +37,7 @@ EXPORTS = [
     "edd_cnn_loss_grad", "edd_cnn_train_step", "edd_solve_batch", "edd_autotune",
     "edd_set_solve_variants", "edd_apply_S_noalloc", "edd_cnn_training_pair",
     "edd_element_energies", "edd_oc_update", "edd_default_topopt_opts", "edd_topopt_run",
+    "edd_solve_gmres",
 ]
 NOALLOC_MAX_INTERIOR_DOFS = 1 << 21
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
@@ -191,6 +192,8 @@ def lib():
     L.edd_apply_K.argtypes = [vp, vp, vp]
     L.edd_solve_interface.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts),
                                       ctypes.POINTER(SolveStats)]
+    L.edd_solve_gmres.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts),
+                                  ctypes.POINTER(SolveStats)]
     L.edd_solve_interior.argtypes = [vp, vp, vp, i32]
     L.edd_apply_S.argtypes = [vp, vp, vp, i32]
     L.edd_apply_S_noalloc.argtypes = [vp, vp, vp, i32]
@@ -393,6 +396,21 @@ class Problem:
         with self._ordered(f, u):
             rc = lib().edd_solve_interface(self.h, pf, pu, ctypes.byref(o), ctypes.byref(st))
         self._check(rc, "edd_solve_interface")
+        return u, st.as_dict()
+
+    def solve_gmres(self, f: torch.Tensor, u: torch.Tensor | None = None, **opts):
+        """The paper's Krylov method: flexible GMRES on K with the block-
+        triangular preconditioner P~ (edd_solve_gmres).  precond selects S~
+        (PC_IDENTITY, PC_HTHETA, PC_SCHUR)."""
+        if u is None:
+            u = torch.zeros_like(f)
+            opts.setdefault("use_initial_guess", 0)
+        o = default_opts(**opts)
+        st = SolveStats()
+        pf, pu = self._v(f, self.ndof, "f"), self._v(u, self.ndof, "u")
+        with self._ordered(f, u):
+            rc = lib().edd_solve_gmres(self.h, pf, pu, ctypes.byref(o), ctypes.byref(st))
+        self._check(rc, "edd_solve_gmres")
         return u, st.as_dict()
 
     # ---- tile shapes -----------------------------------------------------------
