@@ -100,6 +100,11 @@ def parse():
                     help="1: replay the preconditioner apply from a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="topopt: skip the Table 3 sweep")
+    ap.add_argument("--pc-form", type=int, default=None,
+                    help="interface norm form: 0 Htilde inverse Lanczos, 1 H inverse, "
+                         "2 Htilde forward (no inner solves), 3 H forward")
+    ap.add_argument("--lanczos-k", type=int, default=None, help="Lanczos steps per apply")
+    ap.add_argument("--inner", type=int, default=None, help="inner PCG steps per Lanczos step")
     ap.add_argument("--paper-pc", action="store_true",
                     help="topopt: the paper's adaptive preconditioner form (Lanczos to a "
                          "1e-2 change, inner PCG to 1e-3, at most 12 iterations) instead of "
@@ -119,10 +124,14 @@ def make_workload(name):
     return workloads.cantilever2d_uniform_64x32()
 
 
+PC_EXTRA = {}  # preconditioner form and step counts from the command line
+
+
 def solve_opts(path, precond, tol, switch, graphs=0):
     from paper_1501_06211_amd import edd
     o = dict(tol=tol, maxit=5000, use_graphs=graphs,
              precond=edd.PC_HTHETA if precond == "htheta" else edd.PC_IDENTITY)
+    o.update(PC_EXTRA)
     if path == "mixed":
         o.update(precision=edd.MODE_MIXED)
     elif path == "relaxed":
@@ -584,6 +593,12 @@ def one_gpu_guard(args):
 def main():
     args = parse()
     one_gpu_guard(args)
+    if args.pc_form is not None:
+        PC_EXTRA["pc_form"] = args.pc_form
+    if args.lanczos_k is not None:
+        PC_EXTRA["lanczos_kmax"] = args.lanczos_k
+    if args.inner is not None:
+        PC_EXTRA["inner_maxit"] = args.inner
     if args.workload == "sequence":
         run_sequence(args)
         return

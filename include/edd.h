@@ -75,6 +75,17 @@ extern "C" {
 #define EDD_PC_SCHUR 2    /* S~ = S itself, applied by an inner interface     */
                           /* solve to mixed_inner_tol (edd_solve_gmres only)  */
 
+/* edd_solve_opts.pc_form (Section 3, eqs. (NumberEight)-(NumberNine)):
+ * Htilde_theta = M (M^{-1} L)^{1-theta} or H_theta = M + M (M^{-1} L)^{1-theta}
+ * per component, applied by inverse Lanczos on L^{-1} M (every step an inner
+ * face-block PCG on L) or by forward ("truncated") Lanczos on M^{-1} L (every
+ * step one product with L, no inner solves).  H_theta needs no inverse of L,
+ * so its forward form also serves skeletons that do not meet the clamp. */
+#define EDD_PCF_HTILDE_INV 0 /* Htilde_theta, inverse Lanczos (default)       */
+#define EDD_PCF_H_INV 1      /* H_theta, inverse Lanczos                      */
+#define EDD_PCF_HTILDE_FWD 2 /* Htilde_theta, forward Lanczos                 */
+#define EDD_PCF_H_FWD 3      /* H_theta, forward Lanczos                      */
+
 /* stats.flags bits */
 #define EDD_FLAG_TRUE_RES_RESTART 1 /* recursive residual disagreed; restarted */
 #define EDD_FLAG_MIXED_FALLBACK 2   /* mixed path stalled; fell back to FP64   */
@@ -146,6 +157,7 @@ typedef struct edd_solve_opts {
                       /* edd_cnn_setup); 0: off                              */
   int use_graphs;     /* 1: the device-resident preconditioner apply is      */
                       /* captured once into a HIP graph and replayed         */
+  int pc_form;        /* EDD_PCF_*: which interface norm S~ applies and how  */
 } edd_solve_opts;
 
 typedef struct edd_solve_stats {

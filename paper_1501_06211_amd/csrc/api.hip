@@ -575,6 +575,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->interface_weighting = 1;
   o->learned_guess = 0;
   o->use_graphs = 0;
+  o->pc_form = EDD_PCF_HTILDE_INV;
 }
 
 const char *edd_strerror(int code) {
@@ -811,7 +812,9 @@ int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
     return check_hip(p, hipGetLastError());
   }
   if (o->interface_weighting && !p->have_moduli) return EDD_ESTATE;
-  if (o->lanczos_kmax < 1 || o->lanczos_kmax > 64 || o->inner_maxit < 1) return EDD_EINVAL;
+  if (o->lanczos_kmax < 1 || o->lanczos_kmax > 64 || o->inner_maxit < 1 ||
+      o->pc_form < EDD_PCF_HTILDE_INV || o->pc_form > EDD_PCF_H_FWD)
+    return EDD_EINVAL;
   edd_solve_stats st{};
   int rc = precond_apply(p, r_dev, z_dev, o, &st, o->precision == EDD_MODE_MIXED);
   if (rc) return rc;
@@ -1081,7 +1084,8 @@ int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
   if (!(o.tol > 0.0) || o.maxit < 1 || o.outer_maxit < 0) return EDD_EINVAL;
   if (o.precond != EDD_PC_IDENTITY && o.precond != EDD_PC_HTHETA) return EDD_EINVAL;
   if (o.precond == EDD_PC_HTHETA &&
-      (o.lanczos_kmax < 1 || o.lanczos_kmax > 64 || o.inner_maxit < 1 || o.theta > 1.0))
+      (o.lanczos_kmax < 1 || o.lanczos_kmax > 64 || o.inner_maxit < 1 || o.theta > 1.0 ||
+       o.pc_form < EDD_PCF_HTILDE_INV || o.pc_form > EDD_PCF_H_FWD))
     return EDD_EINVAL;
   if (o.precision != EDD_MODE_F64 && o.precision != EDD_MODE_MIXED &&
       o.precision != EDD_MODE_RELAXED)

@@ -234,7 +234,8 @@ extern "C" int edd_solve_gmres(edd_problem *p, const double *f_dev, double *u_de
   if (o.precond != EDD_PC_IDENTITY && o.precond != EDD_PC_HTHETA && o.precond != EDD_PC_SCHUR)
     return EDD_EINVAL;
   if (o.precond != EDD_PC_IDENTITY &&
-      (o.lanczos_kmax < 1 || o.lanczos_kmax > 64 || o.inner_maxit < 1 || o.theta > 1.0))
+      (o.lanczos_kmax < 1 || o.lanczos_kmax > 64 || o.inner_maxit < 1 || o.theta > 1.0 ||
+       o.pc_form < EDD_PCF_HTILDE_INV || o.pc_form > EDD_PCF_H_FWD))
     return EDD_EINVAL;
   if (o.precond == EDD_PC_SCHUR && !(o.mixed_inner_tol > 0.0)) return EDD_EINVAL;
   edd_solve_stats st{};

@@ -70,9 +70,10 @@ struct PcGraphKey {
   double *z = nullptr;
   int k = 0, inner = 0, weighting = 0;
   double theta = 0.0;
+  int form = 0;
   bool operator==(const PcGraphKey &o) const {
     return r == o.r && z == o.z && k == o.k && inner == o.inner && weighting == o.weighting &&
-           theta == o.theta;
+           theta == o.theta && form == o.form;
   }
 };
 

@@ -53,6 +53,19 @@ enum : int {
 constexpr int kMaxFace = 512;  // larger faces fall back to the diagonal
 constexpr int kBlock = 256;
 
+// forms of the interface preconditioner (edd_solve_opts.pc_form)
+inline bool pc_forward(const edd_solve_opts *o) {
+  return o->pc_form == EDD_PCF_HTILDE_FWD || o->pc_form == EDD_PCF_H_FWD;
+}
+inline int pc_fkind(const edd_solve_opts *o) {
+  switch (o->pc_form) {
+    case EDD_PCF_H_INV: return 1;
+    case EDD_PCF_HTILDE_FWD: return 2;
+    case EDD_PCF_H_FWD: return 3;
+    default: return 0;
+  }
+}
+
 namespace {
 
 inline unsigned grid_for(int64_t n) {
@@ -666,6 +679,25 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(int64_t nG, const double *__
   }
 }
 
+// The scalar function applied to the Lanczos tridiagonal (Section 3): with
+// a = 1 - theta, eigenvalues t of T approximate those of C = L^{-1} M
+// (inverse Lanczos, t = 1/lambda) or of A = M^{-1} L (forward, truncated
+// Lanczos, t = lambda), lambda the generalised eigenvalues of L v = lambda M v:
+//   0: t^a     inverse Lanczos, Htilde_theta^{-1} = V Lambda^{-a} V^T
+//   1: t^a / (1 + t^a)      inverse Lanczos, H_theta^{-1} = V (1 + Lambda^a)^{-1} V^T
+//   2: t^{-a}  forward Lanczos, Htilde_theta^{-1}
+//   3: 1 / (1 + t^a)        forward Lanczos, H_theta^{-1}
+// Negative Ritz values (rounding) are clamped to zero.
+__host__ __device__ inline double lanczos_fn(int fkind, double a, double t) {
+  const double l = t > 0.0 ? t : 0.0;
+  switch (fkind) {
+    case 1: { const double q = pow(l, a); return q / (1.0 + q); }
+    case 2: return l > 0.0 ? pow(l, -a) : 0.0;
+    case 3: return 1.0 / (1.0 + pow(l, a));
+    default: return pow(l, a);
+  }
+}
+
 __global__ void k_copy_scal(double *__restrict__ scal, int dst, int src, int n) {
   const int t = threadIdx.x;
   if (t < n) scal[dst + t] = scal[src + t];
@@ -714,9 +746,10 @@ __global__ void k_store_ab(double *__restrict__ scal, int j, int D) {
   scal[P_BETA + c] = b;
 }
 
-// coef[i*D+c] = |b|_M * (T^{pw} e1)_i for the k x k tridiagonal of component
-// c, by cyclic Jacobi rotations; one thread per component (k <= 32)
-__global__ void k_lanczos_coef(double *__restrict__ scal, int k, int D, double pw) {
+// coef[i*D+c] = |b|_M * (f(T) e1)_i for the k x k tridiagonal of component
+// c, by cyclic Jacobi rotations; one thread per component (k <= 32).
+// f is lanczos_fn(fkind, a, .) below.
+__global__ void k_lanczos_coef(double *__restrict__ scal, int k, int D, int fkind, double pw) {
   __shared__ double A[3][32 * 32];
   __shared__ double U[3][32 * 32];
   const int c = threadIdx.x;
@@ -763,8 +796,7 @@ __global__ void k_lanczos_coef(double *__restrict__ scal, int k, int D, double p
   for (int i = 0; i < k; ++i) {
     double y = 0.0;
     for (int j = 0; j < k; ++j) {
-      const double l = fmax(a[j * k + j], 0.0);
-      y += u[i * k + j] * pow(l, pw) * u[0 * k + j];
+      y += u[i * k + j] * lanczos_fn(fkind, pw, a[j * k + j]) * u[0 * k + j];
     }
     scal[P_CO + i * D + c] = b0 * y;
   }
@@ -1177,6 +1209,23 @@ struct PC {
           p->n_rest, p->rest_d, p->skLdiag_d, r, z);
   }
 
+  // One Lanczos operator step on q: w = L^{-1} M q by the face-block PCG
+  // (inverse Lanczos) or w = M^{-1} L q (forward Lanczos, no inner solve);
+  // t is work space.
+  int lanczos_operator(const double *q, double *t, double *w, bool forward, double tol,
+                       int maxit, edd_solve_stats *st) {
+    if (forward) {
+      spmv(q, t);
+      k_cscale<D><<<g1, kBlock, 0, p->stream>>>(nG, p->scal_d, 0, 3, p->skM_d, t, w);
+      return EDD_OK;
+    }
+    k_dscale<D><<<g1, kBlock, 0, p->stream>>>(nG, p->skM_d, q, t);
+    int its = 0;
+    int rc = inner_pcg(t, w, tol, maxit, &its);
+    if (st) st->inner_iterations += its;
+    return rc;
+  }
+
   void spmv(const double *x, double *y) {
     k_spmv<D><<<g1, kBlock, 0, p->stream>>>(nG, p->skL_rowptr_d, p->skL_col_d, p->skL_val_d,
                                              x, y);
@@ -1322,8 +1371,9 @@ void jacobi_eig(int k, std::vector<double> &A, std::vector<double> &U,
   for (int i = 0; i < k; ++i) lam[i] = A[i * k + i];
 }
 
-// y = beta0 * T^{pw} e1 for the symmetric tridiagonal T (alpha, beta)
-void tridiag_power(int k, const double *alpha, const double *beta, double pw,
+// y = beta0 * f(T) e1 for the symmetric tridiagonal T (alpha, beta), f as
+// lanczos_fn(fkind, pw, .)
+void tridiag_power(int k, const double *alpha, const double *beta, int fkind, double pw,
                    double beta0, std::vector<double> &y) {
   std::vector<double> A((size_t)k * k, 0.0), U, lam;
   for (int i = 0; i < k; ++i) {
@@ -1333,8 +1383,7 @@ void tridiag_power(int k, const double *alpha, const double *beta, double pw,
   jacobi_eig(k, A, U, lam);
   y.assign(k, 0.0);
   for (int j = 0; j < k; ++j) {
-    const double l = lam[j] > 0.0 ? lam[j] : 0.0;
-    const double f = std::pow(l, pw) * U[0 * k + j];
+    const double f = lanczos_fn(fkind, pw, lam[j]) * U[0 * k + j];
     for (int i = 0; i < k; ++i) y[i] += beta0 * U[i * k + j] * f;
   }
 }
@@ -1361,13 +1410,11 @@ int apply_device(edd_problem *p, const double *r, double *z, const edd_solve_opt
   k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, 0, 3, p->skM_d, r, t);
   pc.cdots(1, t, t, nullptr, nullptr, p->skM_d, P_B0, 0);
   k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_B0, 1, nullptr, t, Q);
+  const bool fwd = pc_forward(o);
   for (int j = 0; j < k; ++j) {
     double *qj = Q + (int64_t)j * n;
-    k_dscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->skM_d, qj, t);
-    int its = 0;
-    int rc = pc.inner_pcg(t, w, 0.0, o->inner_maxit, &its);
+    int rc = pc.lanczos_operator(qj, t, w, fwd, 0.0, o->inner_maxit, st);
     if (rc) return rc;
-    if (st) st->inner_iterations += its;
     pc.cdots(1, qj, w, nullptr, nullptr, p->skM_d, P_A, 0);
     k_lanczos3<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, qj,
                                                    j > 0 ? Q + (int64_t)(j - 1) * n : nullptr, w);
@@ -1384,7 +1431,7 @@ int apply_device(edd_problem *p, const double *r, double *z, const edd_solve_opt
                                                    Q + (int64_t)(j + 1) * n);
     if (st) st->lanczos_steps++;
   }
-  k_lanczos_coef<<<1, 64, 0, p->stream>>>(p->scal_d, k, D, 1.0 - theta);
+  k_lanczos_coef<<<1, 64, 0, p->stream>>>(p->scal_d, k, D, pc_fkind(o), 1.0 - theta);
   k_ccombine<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, k, Q, p->scal_d + P_CO, 0.0, 1.0, z);
   if (st) st->precond_applications++;
   return hipGetLastError() == hipSuccess ? EDD_OK : EDD_EHIP;
@@ -1400,7 +1447,7 @@ int apply_graph(edd_problem *p, const double *r, double *z, const edd_solve_opts
   const int64_t nG = p->n_gamma;
   const int k = std::min(o->lanczos_kmax, 32);
   const double theta = o->theta >= 0.0 ? o->theta : p->theta_default;
-  const PcGraphKey key{r, z, k, o->inner_maxit, o->interface_weighting ? 1 : 0, theta};
+  const PcGraphKey key{r, z, k, o->inner_maxit, o->interface_weighting ? 1 : 0, theta, o->pc_form};
   if (!p->pc_graph || !(p->pc_graph_key == key)) {
     if (p->pc_graph) {
       hipGraphExecDestroy(p->pc_graph);
@@ -1439,7 +1486,7 @@ int apply_graph(edd_problem *p, const double *r, double *z, const edd_solve_opts
   }
   if (hipGraphLaunch(p->pc_graph, p->stream) != hipSuccess) return EDD_EHIP;
   if (st) {
-    st->inner_iterations += k * o->inner_maxit;
+    if (!pc_forward(o)) st->inner_iterations += k * o->inner_maxit;
     st->lanczos_steps += k;
     st->precond_applications++;
   }
@@ -1476,14 +1523,13 @@ int apply_t(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
   bool conv[3] = {false, false, false};
   for (int c = 0; c < D; ++c) conv[c] = beta0[c] == 0.0;
   int k = 0;
+  const bool fwd = pc_forward(o);
+  const int fkind = pc_fkind(o);
   for (int j = 0; j < kmax; ++j) {
     double *qj = Q + (int64_t)j * n;
-    // w = L^{-1} M q_j
-    k_dscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->skM_d, qj, t);
-    int its = 0;
-    rc = pc.inner_pcg(t, w, o->inner_tol, o->inner_maxit, &its);
+    // w = L^{-1} M q_j (inverse Lanczos) or M^{-1} L q_j (forward)
+    rc = pc.lanczos_operator(qj, t, w, fwd, o->inner_tol, o->inner_maxit, st);
     if (rc) return rc;
-    if (st) st->inner_iterations += its;
     // alpha = <q_j, w>_M ; w -= alpha q_j + beta q_{j-1}
     pc.cdots(1, qj, w, nullptr, nullptr, p->skM_d, P_A, 0);
     k_lanczos3<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, qj,
@@ -1510,7 +1556,7 @@ int apply_t(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
       alpha[c].push_back(p->scal_h[P_A + c]);
       beta[c].push_back(bnext[c]);
       if (beta0[c] == 0.0) { ycur[c].assign(k, 0.0); continue; }
-      tridiag_power(k, alpha[c].data(), beta[c].data(), 1.0 - theta, beta0[c], ycur[c]);
+      tridiag_power(k, alpha[c].data(), beta[c].data(), fkind, 1.0 - theta, beta0[c], ycur[c]);
       if (!conv[c] && j > 0) {
         double dn = 0.0, yn = 0.0;
         for (int i = 0; i < k; ++i) {

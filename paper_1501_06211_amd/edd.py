@@ -23,6 +23,7 @@ F64, F32 = 1, 2
 CLAMP_X0, CLAMP_X1, CLAMP_Y0, CLAMP_Y1, CLAMP_Z0, CLAMP_Z1 = 1, 2, 4, 8, 16, 32
 MODE_F64, MODE_MIXED, MODE_RELAXED = 0, 1, 2
 PC_IDENTITY, PC_HTHETA, PC_SCHUR = 0, 1, 2
+PCF_HTILDE_INV, PCF_H_INV, PCF_HTILDE_FWD, PCF_H_FWD = 0, 1, 2, 3
 FLAG_TRUE_RES_RESTART, FLAG_MIXED_FALLBACK, FLAG_PC_DROPPED = 1, 2, 4
 FLAG_LEARNED_REJECTED = 8
 
@@ -82,6 +83,7 @@ class SolveOpts(ctypes.Structure):
         ("interface_weighting", ctypes.c_int),
         ("learned_guess", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
+        ("pc_form", ctypes.c_int),
     ]
 
 

@@ -222,3 +222,78 @@ def test_iteration_counts_match_the_oracle(dim):
     print(f"{dim}D Hhat_theta exact: GPU {st['iterations']} oracle PCG {its_h}")
     assert abs(st["iterations"] - its_h) <= 2
     prob.close()
+
+
+@pytest.mark.parametrize("weighted", [0, 1])
+@pytest.mark.parametrize("form", ["h_inv", "htilde_fwd", "h_fwd"])
+def test_precond_forms_match_closed_forms_2d(form, weighted):
+    """The other forms of Section 3's interface norm: H_theta = M + M (M^{-1}
+    L)^{1-theta} (eq. (NumberEight)) by inverse Lanczos, and Htilde_theta /
+    H_theta by forward (truncated) Lanczos on M^{-1} L with no inner solves.
+    With as many steps as interface nodes per component, Lanczos spans the
+    whole space and reproduces the oracle's closed forms."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _small2d()
+    prob = make_problem(p)
+    M, L, g = iface.skeleton_matrices(p, lumped=True, weighted=bool(weighted))
+    assert len(g) <= 64
+    theta = 0.6
+    A = iface.h_inv(M, L, theta) if form.startswith("h_") else iface.htilde_inv(M, L, theta)
+    pcf = {"h_inv": edd.PCF_H_INV, "htilde_fwd": edd.PCF_HTILDE_FWD, "h_fwd": edd.PCF_H_FWD}[form]
+    r = np.random.default_rng(3).standard_normal(len(g) * 2)
+    zref = iface.componentwise(A, r, 2)
+    z = to_np(prob.apply_precond(to_cuda(r), precond=edd.PC_HTHETA, theta=theta, pc_form=pcf,
+                                 lanczos_kmax=64, lanczos_tol=0.0, inner_tol=1e-14,
+                                 inner_maxit=1000, interface_weighting=weighted))
+    err = np.linalg.norm(z - zref) / np.linalg.norm(zref)
+    print(f"2D {form} weighted={weighted}: rel err {err:.2e} (n_gamma {len(g)})")
+    assert err <= 1e-7
+    prob.close()
+
+
+@pytest.mark.parametrize("form", ["h_inv", "htilde_fwd", "h_fwd"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_solve_with_each_form(form, dim):
+    """End-to-end solves with each form in its device-resident setting
+    (3 Lanczos steps; forward forms need no inner iterations) match the
+    direct solve."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _small2d() if dim == 2 else _small3d()
+    prob = make_problem(p)
+    uref = fe.solve_direct(p)
+    pcf = {"h_inv": edd.PCF_H_INV, "htilde_fwd": edd.PCF_HTILDE_FWD, "h_fwd": edd.PCF_H_FWD}[form]
+    kmax = 3 if form == "h_inv" else 8
+    u, st = prob.solve(to_cuda(p.f), tol=1e-11, maxit=3000, pc_form=pcf, lanczos_kmax=kmax)
+    err = np.linalg.norm(to_np(u) - uref) / np.linalg.norm(uref)
+    print(f"{dim}D {form}: its={st['iterations']} inner={st['inner_iterations']} u_err={err:.1e}")
+    assert err <= 1e-8
+    if form != "h_inv":
+        assert st["inner_iterations"] == 0
+    prob.close()
+
+
+def test_h_theta_on_a_skeleton_away_from_the_clamp():
+    """Two subdomains side by side along x: the skeleton's L is singular (it
+    does not meet the clamp), so Htilde_theta is undefined, but H_theta is
+    not: its forward form matches the closed form and preconditions the
+    solve."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = w.cantilever2d(32, 16, cuts=(np.array([0, 16, 32]), np.array([0, 16])))
+    p.E = 1e-3 + np.random.default_rng(4).uniform(0, 1, p.n_el) ** 3
+    prob = make_problem(p)
+    M, L, g = iface.skeleton_matrices(p, lumped=True, weighted=True)
+    assert np.linalg.eigvalsh(L.toarray()).min() < 1e-12  # singular
+    r = np.random.default_rng(5).standard_normal(len(g) * 2)
+    zref = iface.componentwise(iface.h_inv(M, L, 0.5), r, 2)
+    z = to_np(prob.apply_precond(to_cuda(r), precond=edd.PC_HTHETA, theta=0.5,
+                                 pc_form=edd.PCF_H_FWD, lanczos_kmax=len(g), lanczos_tol=0.0,
+                                 inner_tol=1e-14, inner_maxit=10))
+    assert np.linalg.norm(z - zref) <= 1e-7 * np.linalg.norm(zref)
+    u, st = prob.solve(to_cuda(p.f), tol=1e-12, maxit=2000, pc_form=edd.PCF_H_FWD,
+                       lanczos_kmax=8)
+    uref = fe.solve_direct(p)
+    assert np.linalg.norm(to_np(u) - uref) <= 1e-8 * np.linalg.norm(uref)
+    prob.close()
