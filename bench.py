@@ -104,6 +104,9 @@ def parse():
                     help="interface norm form: 0 Htilde inverse Lanczos, 1 H inverse, "
                          "2 Htilde forward (no inner solves), 3 H forward")
     ap.add_argument("--lanczos-k", type=int, default=None, help="Lanczos steps per apply")
+    ap.add_argument("--dissect", type=int, default=-1,
+                    help="interior dissection rule (edd_mesh_desc.dissect): -1 auto, 0 never, "
+                         "1 every interior, 2 only interiors above 1.5x the median band work")
     ap.add_argument("--inner", type=int, default=None, help="inner PCG steps per Lanczos step")
     ap.add_argument("--paper-pc", action="store_true",
                     help="topopt: the paper's adaptive preconditioner form (Lanczos to a "
@@ -640,7 +643,7 @@ def main():
         if not group:
             continue
         prec = edd.F64 if prec_name == "f64" else edd.F64 | edd.F32
-        prob = edd.Problem.from_workload(w, factor_precision=prec)
+        prob = edd.Problem.from_workload(w, factor_precision=prec, dissect=args.dissect)
         prob.set_element_moduli(E)
         pv = prob.autotune()  # timed once per shape class, outside the timed region
         log(f"{prec_name}: autotuned substitution variants (FP64, FP32): {pv}")

@@ -121,7 +121,8 @@ typedef struct edd_mesh_desc {
                         /* band work exceeds 1.5x the median, or when there */
                         /* are fewer subdomains than compute units (then    */
                         /* every interior of >= 3000 dofs), 0: never, 1:    */
-                        /* every interior with at least 5 planes; 2D        */
+                        /* every interior with at least 5 planes, 2: only   */
+                        /* interiors above 1.5x the median band work; 2D    */
                         /* problems never split                             */
 } edd_mesh_desc;
 

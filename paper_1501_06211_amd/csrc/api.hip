@@ -616,7 +616,7 @@ static int validate_desc(const edd_mesh_desc *d) {
   if (!(d->nu > -1.0 && d->nu < 0.5)) return EDD_EINVAL;
   if ((d->clamp_faces & ((1 << (2 * d->dim)) - 1)) == 0) return EDD_EINVAL;
   if (!(d->factor_precision & (EDD_F64 | EDD_F32))) return EDD_EINVAL;
-  if (d->dissect < -1 || d->dissect > 1) return EDD_EINVAL;
+  if (d->dissect < -1 || d->dissect > 2) return EDD_EINVAL;
   int64_t nodes = 1;
   for (int a = 0; a < d->dim; ++a) {
     if (d->nel[a] < 1 || d->nel[a] > (1 << 20)) return EDD_EINVAL;

@@ -186,7 +186,7 @@ int build_geometry(edd_problem *p, const edd_mesh_desc *d) {
     const int64_t n = box_dofs(bx);
     // more band blocks than subdomains keeps more compute units streaming
     split[i] = p->dissect == 1 || work[i] > 1.5 * median ||
-               (p->n_sub < p->n_cu && n >= 3000);
+               (p->dissect == -1 && p->n_sub < p->n_cu && n >= 3000);
   }
 
   // band blocks, interior dofs subdomain by subdomain: [half a][half b][sep]
