@@ -646,7 +646,8 @@ def main():
         prob = edd.Problem.from_workload(w, factor_precision=prec, dissect=args.dissect)
         prob.set_element_moduli(E)
         pv = prob.autotune()  # timed once per shape class, outside the timed region
-        log(f"{prec_name}: autotuned substitution variants (FP64, FP32): {pv}")
+        log(f"{prec_name}: autotuned (substitution FP64, FP32; element tiles all, interior, "
+            f"interface): {pv}")
         if info is None:
             info, variants = prob.info, pv
         for leg in group:
@@ -736,7 +737,11 @@ def main():
         "layout": {"band_blocks": info["band_blocks"], "band_entries": info["factor_entries"],
                    "coupling_entries": info["coupling_entries"],
                    "interior_dofs": info["n_interior_dofs"], "gamma_nodes": info["n_gamma"],
-                   "substitution_variants": list(variants)},
+                   "autotuned": {"substitution_fp64": variants[0],
+                                 "substitution_fp32": variants[1],
+                                 "element_tile_all": variants[2],
+                                 "element_tile_interior": variants[3],
+                                 "element_tile_interface": variants[4]}},
         "config": {"workload": w.name, "ndof": int(w.ndof), "subdomains": int(w.n_sub),
                    "path": head, "precond": args.precond, "tol": args.tol,
                    "step": "set_element_moduli + solve from zero",

@@ -311,19 +311,36 @@ int edd_solve_batch(edd_problem *const *ps, int n, const double *const *f_dev,
                     double *const *u_dev, const edd_solve_opts *o,
                     edd_solve_stats *stats, int nthreads);
 
-/* Autotuner for the batched interior substitution: times every substitution
- * variant valid for this problem's bands (1-3: one row per thread with an
- * owner wavefront per diagonal block, 64/256/512 threads per subdomain;
- * 4-6: wide bands, a dedicated chain wavefront and 1024 threads, two load
- * chunk widths, the narrower one also double-buffered) on the current factors, for FP64 and (if present) FP32
- * factors, and keeps the fastest.  Results are cached per shape class
- * (device, dimension, subdomain count, band extents, factor precisions) for
- * the process;
- * force != 0 re-times.  variants (2 ints, FP64 then FP32) may be NULL.
- * Needs edd_set_element_moduli.  Synchronises. */
+/* Autotuner of the tile shapes (the benchmark spec's project-written tuner):
+ *  - the batched interior substitution: every variant valid for this
+ *    problem's bands (1-3: one row per thread with an owner wavefront per
+ *    diagonal block, 64/256/512 threads per subdomain; 4-6: wide bands, a
+ *    dedicated chain wavefront and 1024 threads, two load chunk widths, the
+ *    narrower one also double-buffered), for FP64 and (if present) FP32
+ *    factors, timed on the current factors;
+ *  - the element kernel: node tiles of 16x16 / 32x8 / 64x4 (2D) or 8x8x4 /
+ *    16x4x4 / 16x8x2 (3D) nodes (every shape gives bitwise the same result),
+ *    chosen separately for the full product, the product on interior nodes
+ *    and the product on interface nodes (the two halves of an S apply).
+ * The fastest of each is kept.  Choices are cached per (device
+ * architecture, kernel family, shape class: dimension, band extents and
+ * factor precisions for the substitution, the node grid for the element
+ * kernel) in memory for the process and, after edd_autotune_cache, in that
+ * file; force != 0 re-times.  variants (5 ints: FP64 and FP32 substitution
+ * variants, element tile shapes for all / interior / interface nodes) may
+ * be NULL.  Needs edd_set_element_moduli.
+ * Synchronises. */
 int edd_autotune(edd_problem *p, int force, int *variants);
+/* Use (and create or update) the autotuner cache file at path (NULL or "":
+ * memory only): loads the file's entries, replacing the in-memory cache.
+ * Text, one line per entry: family, key, values.  Not thread-safe against
+ * concurrent edd_autotune calls in other threads. */
+int edd_autotune_cache(const char *path);
 /* Choose the substitution variants by hand (0 = default by bandwidth). */
 int edd_set_solve_variants(edd_problem *p, const int *variants);
+/* Choose the element kernel's node-tile shape by hand (0..2, as above) for
+ * all three kinds of target. */
+int edd_set_apply_variant(edd_problem *p, int variant);
 
 /* ---- correction network (an addition to the paper's method) -----------
  * A convolution network on the node grid proposes a displacement correction

@@ -23,6 +23,7 @@
 #include <thread>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
 
 #include "internal.h"
 
@@ -885,69 +886,182 @@ int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host) {
   return EDD_OK;
 }
 
+// Autotuner cache: in memory for the process, and in a text file when one is
+// set (edd_autotune_cache): one line per tuned (kernel family, shape class),
+//   <family> <key> <value> [<value>]
+// with family band_solve (FP64 and FP32 substitution variants) or apply_K
+// (node-tile shape), key = architecture|shape class.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, std::vector<int>> g_tune;
+std::string g_tune_path;
+
+void tune_load_locked() {
+  g_tune.clear();
+  if (g_tune_path.empty()) return;
+  FILE *fh = std::fopen(g_tune_path.c_str(), "r");
+  if (!fh) return;
+  char line[1024];
+  while (std::fgets(line, sizeof line, fh)) {
+    char fam[64], key[768];
+    int v[3] = {0, 0, 0};
+    const int n = std::sscanf(line, "%63s %767s %d %d %d", fam, key, &v[0], &v[1], &v[2]);
+    if (n >= 3) g_tune[std::string(fam) + " " + key] = std::vector<int>(v, v + (n - 2));
+  }
+  std::fclose(fh);
+}
+
+void tune_save_locked() {
+  if (g_tune_path.empty()) return;
+  const std::string tmp = g_tune_path + ".tmp";
+  FILE *fh = std::fopen(tmp.c_str(), "w");
+  if (!fh) return;
+  for (const auto &kv : g_tune) {
+    std::fprintf(fh, "%s", kv.first.c_str());
+    for (int v : kv.second) std::fprintf(fh, " %d", v);
+    std::fprintf(fh, "\n");
+  }
+  std::fclose(fh);
+  std::rename(tmp.c_str(), g_tune_path.c_str());
+}
+}  // namespace
+
+int edd_autotune_cache(const char *path) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_path = path ? path : "";
+  tune_load_locked();
+  return EDD_OK;
+}
+
 int edd_autotune(edd_problem *p, int force, int *variants) {
   if (!p) return EDD_EINVAL;
   if (!p->have_moduli) return EDD_ESTATE;
-  static std::mutex mu;
-  static std::map<std::string, std::array<int, 2>> cache;
   hipDeviceProp_t prop;
   int rc = check_hip(p, hipGetDeviceProperties(&prop, p->device));
   if (rc) return rc;
-  // shape class: device, dimension, subdomain count and band extents
-  const std::string key = std::string(prop.gcnArchName) + "|" + std::to_string(p->g.dim) + "|" +
-                          std::to_string(p->n_blk) + "|" + std::to_string(p->max_kd) + "|" +
-                          std::to_string(p->max_np) + "|" + std::to_string(p->fac_entries) +
-                          "|" + std::to_string(p->factor_precision);
+  // shape classes: the substitution's by band extents and factor
+  // precisions, the element kernel's by dimension and node grid
+  const std::string arch = prop.gcnArchName;
+  const std::string kb = "band_solve " + arch + "|" + std::to_string(p->g.dim) + "|" +
+                         std::to_string(p->n_blk) + "|" + std::to_string(p->max_kd) + "|" +
+                         std::to_string(p->max_np) + "|" + std::to_string(p->fac_entries) + "|" +
+                         std::to_string(p->factor_precision);
+  const std::string ka = "apply_K " + arch + "|" + std::to_string(p->g.dim) + "|" +
+                         std::to_string(p->g.nn[0]) + "x" + std::to_string(p->g.nn[1]) + "x" +
+                         std::to_string(p->g.nn[2]);
+  bool need_band = true, need_apply = true;
   {
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(key);
-    if (!force && it != cache.end()) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(kb);
+    if (!force && it != g_tune.end() && it->second.size() == 2 &&
+        band_solve_variant_ok(p, it->second[0]) && band_solve_variant_ok(p, it->second[1])) {
       p->solve_variant[0] = it->second[0];
       p->solve_variant[1] = it->second[1];
-      if (variants) { variants[0] = it->second[0]; variants[1] = it->second[1]; }
-      return EDD_OK;
+      need_band = false;
     }
-  }
-  hipEvent_t e0, e1;
-  rc = check_hip(p, hipEventCreate(&e0));
-  if (rc) return rc;
-  rc = check_hip(p, hipEventCreate(&e1));
-  if (rc) return rc;
-  double *b = p->w_I[0], *x = p->w_I[1];
-  launch_fill(p, p->n_idofs, 1.0, b);
-  const bool kt = p->kt_enabled;
-  p->kt_enabled = false;
-  for (int f = 0; f < 2 && rc == 0; ++f) {
-    const int prec = f ? EDD_F32 : EDD_F64;
-    if (f && !p->fac32_d) break;
-    int best = 0;
-    float best_ms = 0.0f;
-    for (int v = 1; v <= kBandSolveVariants && rc == 0; ++v) {
-      if (!band_solve_variant_ok(p, v)) continue;
-      p->solve_variant[f] = v;
-      launch_band_solve(p, prec, b, x);  // warm-up (first-launch costs)
-      hipEventRecord(e0, p->stream);
-      for (int r = 0; r < 3; ++r) launch_band_solve(p, prec, b, x);
-      hipEventRecord(e1, p->stream);
-      rc = check_hip(p, hipEventSynchronize(e1));
-      float ms = 0.0f;
-      if (!rc) rc = check_hip(p, hipEventElapsedTime(&ms, e0, e1));
-      if (!rc && (best == 0 || ms < best_ms)) {
-        best = v;
-        best_ms = ms;
+    auto ia = g_tune.find(ka);
+    if (!force && ia != g_tune.end() && ia->second.size() == 3) {
+      bool ok = true;
+      for (int t = 0; t < 3; ++t) ok = ok && ia->second[t] >= 0 && ia->second[t] < kApplyVariants;
+      if (ok) {
+        for (int t = 0; t < 3; ++t) p->apply_variant[t] = ia->second[t];
+        need_apply = false;
       }
     }
-    p->solve_variant[f] = best;
   }
-  p->kt_enabled = kt;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  if (rc) return rc;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    cache[key] = {p->solve_variant[0], p->solve_variant[1]};
+  if (need_band || need_apply) {
+    hipEvent_t e0, e1;
+    rc = check_hip(p, hipEventCreate(&e0));
+    if (rc) return rc;
+    rc = check_hip(p, hipEventCreate(&e1));
+    if (rc) return rc;
+    auto time_it = [&](auto &&launch, int reps, float *ms) {
+      launch();  // warm-up (first-launch costs)
+      hipEventRecord(e0, p->stream);
+      for (int r = 0; r < reps; ++r) launch();
+      hipEventRecord(e1, p->stream);
+      int c = check_hip(p, hipEventSynchronize(e1));
+      if (!c) c = check_hip(p, hipEventElapsedTime(ms, e0, e1));
+      return c;
+    };
+    const bool kt = p->kt_enabled;
+    p->kt_enabled = false;
+    if (need_band) {
+      double *b = p->w_I[0], *x = p->w_I[1];
+      launch_fill(p, p->n_idofs, 1.0, b);
+      for (int f = 0; f < 2 && rc == 0; ++f) {
+        const int prec = f ? EDD_F32 : EDD_F64;
+        if (f && !p->fac32_d) break;
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int v = 1; v <= kBandSolveVariants && rc == 0; ++v) {
+          if (!band_solve_variant_ok(p, v)) continue;
+          p->solve_variant[f] = v;
+          float ms = 0.0f;
+          rc = time_it([&] { launch_band_solve(p, prec, b, x); }, 3, &ms);
+          if (!rc && (best == 0 || ms < best_ms)) {
+            best = v;
+            best_ms = ms;
+          }
+        }
+        p->solve_variant[f] = best;
+      }
+    }
+    if (need_apply && rc == 0) {
+      // timed on a vector of ones into a buffer of its own (allocated once)
+      double *u = p->w_full[0];
+      if (!p->tune_y_d) p->tune_y_d = (double *)dev_alloc(p, sizeof(double) * p->ndof);
+      double *y = p->tune_y_d;
+      if (!y) rc = EDD_ENOMEM;
+      if (!rc) launch_fill(p, p->ndof, 1.0, u);
+      // each kind of target on its own: all nodes, interior nodes (packed
+      // interior output), interface nodes (packed interface output)
+      double *oI = p->w_I[0], *oG = p->w_G[0];
+      for (int t = 0; t < 3 && rc == 0; ++t) {
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int v = 0; v < kApplyVariants && rc == 0; ++v) {
+          p->apply_variant[t] = v;
+          float ms = 0.0f;
+          if (t == 0)
+            rc = time_it([&] { launch_apply_full(p, u, y); }, 5, &ms);
+          else if (t == 1)
+            rc = time_it([&] { launch_apply_mapped(p, p->inode_d, p->n_inodes, nullptr, 0.0, y,
+                                                   1.0, nullptr, 1.0, oI); }, 5, &ms);
+          else
+            rc = time_it([&] { launch_apply_mapped(p, p->gnode_d, p->n_gamma, y, 1.0, nullptr,
+                                                   0.0, u, -1.0, oG); }, 5, &ms);
+          if (!rc && (v == 0 || ms < best_ms)) {
+            best = v;
+            best_ms = ms;
+          }
+        }
+        p->apply_variant[t] = best;
+      }
+      launch_fill(p, p->ndof, 0.0, u);
+    }
+    p->kt_enabled = kt;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (need_band) g_tune[kb] = {p->solve_variant[0], p->solve_variant[1]};
+    if (need_apply) g_tune[ka] = {p->apply_variant[0], p->apply_variant[1], p->apply_variant[2]};
+    tune_save_locked();
   }
-  if (variants) { variants[0] = p->solve_variant[0]; variants[1] = p->solve_variant[1]; }
+  if (variants) {
+    variants[0] = p->solve_variant[0];
+    variants[1] = p->solve_variant[1];
+    variants[2] = p->apply_variant[0];
+    variants[3] = p->apply_variant[1];
+    variants[4] = p->apply_variant[2];
+  }
+  return EDD_OK;
+}
+
+int edd_set_apply_variant(edd_problem *p, int variant) {
+  if (!p || variant < 0 || variant >= kApplyVariants) return EDD_EINVAL;
+  for (int t = 0; t < 3; ++t) p->apply_variant[t] = variant;
   return EDD_OK;
 }
 

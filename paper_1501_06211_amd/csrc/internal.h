@@ -152,6 +152,9 @@ struct edd_problem {
   float *rac32_d = nullptr;
   bool have_moduli = false;
   int solve_variant[2] = {0, 0};  // substitution variant, FP64 / FP32 factors
+  int apply_variant[3] = {0, 0, 0};  // node-tile shape of the element kernel (0..2) for
+                                     // all nodes, interior targets, interface targets
+  double *tune_y_d = nullptr;     // output buffer of the element-kernel timings
 
   // skeleton operators of the interface preconditioner
   int sk_state = -1;            // weighting the device operators hold (-1 none)
@@ -274,6 +277,7 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x);
 bool band_solve_variant_ok(const edd_problem *p, int v);
 constexpr int kBandSolveVariants = 6;
+constexpr int kApplyVariants = 3;  // node-tile shapes of the element kernel
 
 // kernels_vec.hip
 // dots: out[k] = sum_i a_k[i] * b_k[i] for k < nd (nd <= 4), written to

@@ -137,23 +137,43 @@ __global__ __launch_bounds__(kBlock) void k_apply(
 // enter with modulus zero.  TGT 0: every node, out[D node + c] (Dirichlet
 // rows 0); TGT 1: interior nodes, out[code + c]; TGT 2: interface nodes,
 // out[D gamma + c]; for TGT 1, 2 out = sy y + base[D node + c].
-template <int D>
+// Node tiles of 256 nodes (one per thread); the autotuner picks the shape
+// for each kind of target (edd_problem::apply_variant).  The shape changes only how the source
+// halo is staged, never the arithmetic of a node's row, so every shape gives
+// bitwise the same result.
+template <int D, int V>
 struct Tile;
 template <>
-struct Tile<2> {
+struct Tile<2, 0> {
   static constexpr int X = 16, Y = 16, Z = 1;
 };
 template <>
-struct Tile<3> {
+struct Tile<2, 1> {
+  static constexpr int X = 32, Y = 8, Z = 1;
+};
+template <>
+struct Tile<2, 2> {
+  static constexpr int X = 64, Y = 4, Z = 1;
+};
+template <>
+struct Tile<3, 0> {
   static constexpr int X = 8, Y = 8, Z = 4;
 };
+template <>
+struct Tile<3, 1> {
+  static constexpr int X = 16, Y = 4, Z = 4;
+};
+template <>
+struct Tile<3, 2> {
+  static constexpr int X = 16, Y = 8, Z = 2;
+};
 
-template <int D, int MODE, int TGT>
+template <int D, int MODE, int TGT, int V>
 __global__ __launch_bounds__(256) void k_apply_tiled(
     Geom g, const double *__restrict__ K0, const double *__restrict__ E,
     const int *__restrict__ nmap, Src src, const double *__restrict__ base, double sy,
     double *__restrict__ out) {
-  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+  constexpr int TX = Tile<D, V>::X, TY = Tile<D, V>::Y, TZ = Tile<D, V>::Z;
   constexpr int HX = TX + 2, HY = TY + 2, HZ = (D == 3) ? TZ + 2 : 1;
   constexpr int EX = TX + 1, EY = TY + 1, EZ = (D == 3) ? TZ + 1 : 1;
   constexpr int NC = (D == 3) ? 8 : 4;
@@ -418,12 +438,22 @@ inline unsigned grid_for(int64_t n) {
 
 }  // namespace
 
+template <int D, int MODE, int TGT, int V>
+void apply_tiled_v(edd_problem *p, const Src &s, const double *base, double sy, double *out) {
+  using T = Tile<D, V>;
+  dim3 grid((p->g.nn[0] + T::X - 1) / T::X, (p->g.nn[1] + T::Y - 1) / T::Y,
+            (p->g.nn[2] + T::Z - 1) / T::Z);
+  k_apply_tiled<D, MODE, TGT, V><<<grid, 256, 0, p->stream>>>(p->g, p->K0_d, p->E_d, p->nmap_d,
+                                                             s, base, sy, out);
+}
+
 template <int D, int MODE, int TGT>
 void apply_tiled(edd_problem *p, const Src &s, const double *base, double sy, double *out) {
-  dim3 grid((p->g.nn[0] + Tile<D>::X - 1) / Tile<D>::X, (p->g.nn[1] + Tile<D>::Y - 1) / Tile<D>::Y,
-            (p->g.nn[2] + Tile<D>::Z - 1) / Tile<D>::Z);
-  k_apply_tiled<D, MODE, TGT><<<grid, 256, 0, p->stream>>>(p->g, p->K0_d, p->E_d, p->nmap_d,
-                                                          s, base, sy, out);
+  switch (p->apply_variant[TGT]) {
+    case 1: apply_tiled_v<D, MODE, TGT, 1>(p, s, base, sy, out); break;
+    case 2: apply_tiled_v<D, MODE, TGT, 2>(p, s, base, sy, out); break;
+    default: apply_tiled_v<D, MODE, TGT, 0>(p, s, base, sy, out); break;
+  }
 }
 
 void launch_apply_full(edd_problem *p, const double *u, double *y) {

@@ -38,7 +38,7 @@ EXPORTS = [
     "edd_cnn_loss_grad", "edd_cnn_train_step", "edd_solve_batch", "edd_autotune",
     "edd_set_solve_variants", "edd_apply_S_noalloc", "edd_cnn_training_pair",
     "edd_element_energies", "edd_oc_update", "edd_default_topopt_opts", "edd_topopt_run",
-    "edd_solve_gmres",
+    "edd_solve_gmres", "edd_autotune_cache", "edd_set_apply_variant",
 ]
 NOALLOC_MAX_INTERIOR_DOFS = 1 << 21
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
@@ -214,6 +214,8 @@ def lib():
                                   ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(SolveStats), i32]
     L.edd_autotune.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    L.edd_autotune_cache.argtypes = [ctypes.c_char_p]
+    L.edd_set_apply_variant.argtypes = [vp, i32]
     L.edd_set_solve_variants.argtypes = [vp, ctypes.POINTER(i32)]
     L.edd_cnn_setup.argtypes = [vp, i32]
     L.edd_cnn_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -417,10 +419,15 @@ class Problem:
 
     # ---- tile shapes -----------------------------------------------------------
     def autotune(self, force=False):
-        v = (ctypes.c_int * 2)()
+        """(FP64 substitution variant, FP32 substitution variant, element tile
+        shapes for all / interior / interface nodes) chosen by edd_autotune."""
+        v = (ctypes.c_int * 5)()
         with self._ordered():
             self._check(lib().edd_autotune(self.h, int(force), v), "edd_autotune")
-        return int(v[0]), int(v[1])
+        return tuple(int(x) for x in v)
+
+    def set_apply_variant(self, v):
+        self._check(lib().edd_set_apply_variant(self.h, int(v)), "edd_set_apply_variant")
 
     def set_solve_variants(self, f64, f32):
         v = (ctypes.c_int * 2)(int(f64), int(f32))
@@ -626,6 +633,11 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def set_autotune_cache(path):
+    """edd_autotune_cache: persist autotuner choices in a file (None: memory only)."""
+    lib().edd_autotune_cache(None if path is None else os.fsencode(path))
 
 
 def solve_batch(problems, fs, us, nthreads=0, **opts):

@@ -135,10 +135,11 @@ def test_autotune_picks_valid_variants_and_caches():
     p64 = make_problem(p, factor_precision=edd.F64)
     v64 = p64.autotune(force=True)
     assert 1 <= v64[0] <= 6 and v64[1] == 0  # no FP32 factors: nothing to tune
+    assert all(0 <= x <= 2 for x in v64[2:])
     p64.close()
     prob = make_problem(p)
     v = prob.autotune()  # factor precisions are part of the cache key
-    assert all(1 <= x <= 6 for x in v)
+    assert all(1 <= x <= 6 for x in v[:2]) and all(0 <= x <= 2 for x in v[2:])
     prob2 = make_problem(p)
     assert prob2.autotune() == v  # same shape class: cached
     u, st = prob2.solve(to_cuda(p.f), tol=1e-12, maxit=3000)
@@ -200,3 +201,55 @@ def test_batch_matches_single_solves_and_the_oracle():
           f"latency ms {np.round(lat, 1).tolist()}")
     for prob in probs:
         prob.close()
+
+
+def test_autotune_cache_file(tmp_path):
+    """Choices persist in the cache file, one line per (kernel family, shape
+    class), and are read back from it without re-timing."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    path = str(tmp_path / "tune.txt")
+    edd.set_autotune_cache(path)
+    try:
+        p = _wide()
+        prob = make_problem(p)
+        v = prob.autotune(force=True)
+        lines = open(path).read().splitlines()
+        fams = sorted(l.split()[0] for l in lines)
+        assert fams == ["apply_K", "band_solve"]
+        # edit the stored tile shapes; a reload must return the file's values
+        other = [(x + 1) % 3 for x in v[2:]]
+        edited = [(" ".join(l.split()[:2] + [str(x) for x in other])
+                   if l.startswith("apply_K") else l) for l in lines]
+        open(path, "w").write("\n".join(edited) + "\n")
+        edd.set_autotune_cache(path)
+        prob2 = make_problem(p)
+        v2 = prob2.autotune()
+        assert v2 == (v[0], v[1], *other)
+        prob.close()
+        prob2.close()
+    finally:
+        edd.set_autotune_cache(None)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_element_tile_shapes_are_bitwise_equal(dim):
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    rng = np.random.default_rng(8)
+    if dim == 2:
+        p = w.cantilever2d(45, 23, cuts=(np.array([0, 20, 45]), np.array([0, 11, 23])))
+    else:
+        p = w.cantilever3d(19, 11, 9, cuts=(np.array([0, 9, 19]), np.array([0, 11]),
+                                            np.array([0, 4, 9])))
+    p.E = 1e-3 + rng.uniform(0, 1, p.n_el) ** 3
+    prob = make_problem(p)
+    u = rng.standard_normal(p.ndof)
+    ref = fe.apply_K_elementwise(p, u)
+    ys = []
+    for v in range(3):
+        prob.set_apply_variant(v)
+        ys.append(to_np(prob.apply_K(to_cuda(u))))
+    assert all(np.array_equal(ys[0], y) for y in ys[1:])
+    assert np.linalg.norm(ys[0] - ref) <= 1e-14 * np.linalg.norm(ref)
+    prob.close()
