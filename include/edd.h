@@ -157,7 +157,18 @@ typedef struct edd_solve_opts {
                       /* interface energy error along it (needs              */
                       /* edd_cnn_setup); 0: off                              */
   int use_graphs;     /* 1: the device-resident preconditioner apply is      */
-                      /* captured once into a HIP graph and replayed         */
+                      /* captured once into a HIP graph and replayed;        */
+                      /* n >= 2: the interface iteration itself runs as      */
+                      /* replays of a captured graph of n iterations (up to  */
+                      /* 64; device-resident preconditioner, FP64 or mixed   */
+                      /* mode): the window comes from a device iteration     */
+                      /* index and a device flag marks convergence, read by  */
+                      /* the host once per replay.  Up to the first         */
+                      /* converged iteration the arithmetic is bitwise that  */
+                      /* of the host-driven loop, which checks every 4       */
+                      /* iterations; the steps a replay runs after that only */
+                      /* refine u.  Kernel timing is not recorded inside the */
+                      /* graph.                                              */
   int pc_form;        /* EDD_PCF_*: which interface norm S~ applies and how  */
 } edd_solve_opts;
 

@@ -197,6 +197,124 @@ static void back_substitute(edd_problem *p, const double *f, const double *uG, d
   launch_scatter_solution(p, t, uG, u);
 }
 
+// The iterations of interface_fcg as replays of a captured graph of
+// o->use_graphs iterations (device-resident preconditioner, no precision
+// switch): the window position comes from the device iteration index, each
+// new direction goes through fixed buffers into its ring slot, and a device
+// flag records the first iteration whose residual met tol_abs.  The host
+// reads the flag once per replay; the iterations of the last replay that
+// follow convergence only refine x (the reported count is the first
+// converged iteration).  Up to that iteration the arithmetic, and its order,
+// is that of the host-driven loop.  Entered with r and x set and rr = r.r.
+static int fcg_graph_iterations(edd_problem *p, double *x, int prec, double tol_abs,
+                                const edd_solve_opts *o, edd_solve_stats *st, int maxit,
+                                int cap, int *iters) {
+  const int64_t nG = p->n_gamma * p->g.dim;
+  const int N = std::max(2, std::min(o->use_graphs, 64));
+  double *r = p->w_G[1], *z = p->w_G[2];
+  if (!p->gr_p_d) {
+    p->gr_p_d = (double *)dev_alloc(p, sizeof(double) * std::max<int64_t>(1, nG));
+    p->gr_q_d = (double *)dev_alloc(p, sizeof(double) * std::max<int64_t>(1, nG));
+    if (!p->gr_p_d || !p->gr_q_d) return EDD_ENOMEM;
+  }
+  double *pn = p->gr_p_d, *qn = p->gr_q_d;
+  const bool pc_identity = o->precond == EDD_PC_IDENTITY;
+  edd_solve_opts oc = *o;
+  oc.use_graphs = 0;  // the preconditioner's kernels go into this graph directly
+  const double th = o->theta;
+  int64_t key[12] = {N, cap, prec, (int64_t)(uintptr_t)x, o->precond, o->lanczos_kmax,
+                     o->inner_maxit, o->interface_weighting, o->pc_form, 0, 0, nG};
+  std::memcpy(&key[9], &th, sizeof th);
+  if (!p->fcg_graph || std::memcmp(key, p->fcg_graph_key, sizeof key) != 0) {
+    if (p->fcg_graph) {
+      hipGraphExecDestroy(p->fcg_graph);
+      p->fcg_graph = nullptr;
+    }
+    if (!p->cap_stream &&
+        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      p->cap_stream = nullptr;
+      return EDD_EHIP;
+    }
+    // work buffers the preconditioner allocates on first use: allocate now,
+    // outside the capture
+    if (!pc_identity) {
+      int rc = precond_apply(p, r, z, &oc, nullptr, false);
+      if (rc) return rc;
+      rc = check_hip(p, hipStreamSynchronize(p->stream));
+      if (rc) return rc;
+    }
+    hipStream_t saved = p->stream;
+    const bool kt = p->kt_enabled;
+    p->kt_enabled = false;
+    p->stream = p->cap_stream;
+    hipGraph_t graph = nullptr;
+    int rc = EDD_OK;
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = EDD_EHIP;
+    } else {
+      for (int it = 0; it < N && rc == EDD_OK; ++it) {
+        const double *zp = r;
+        if (!pc_identity) {
+          rc = precond_apply(p, r, z, &oc, nullptr, false);
+          zp = z;
+        }
+        launch_window_dots_dev(p, nG, cap, p->winQ_d, zp, S_C_BASE);
+        launch_window_combine_dev(p, nG, cap, p->winP_d, S_C_BASE, S_PQ_BASE, zp, pn);
+        apply_S(p, pn, qn, prec);
+        {
+          const double *a[2] = {pn, pn}, *b[2] = {qn, r};
+          launch_dots(p, nG, 2, a, b, S_PQCUR);
+        }
+        launch_cg_update(p, nG, S_PR, S_PQCUR, x, pn, r, qn, kSlotGRR, kSlotGPQ, S_BREAK);
+        launch_ring_store(p, nG, cap, pn, p->winP_d);
+        launch_ring_store(p, nG, cap, qn, p->winQ_d);
+        launch_iter_end(p, cap, S_PQ_BASE);
+      }
+      if (hipStreamEndCapture(p->cap_stream, &graph) != hipSuccess) rc = EDD_EHIP;
+    }
+    p->stream = saved;
+    p->kt_enabled = kt;
+    if (rc == EDD_OK && graph &&
+        hipGraphInstantiate(&p->fcg_graph, graph, nullptr, nullptr, 0) != hipSuccess) {
+      p->fcg_graph = nullptr;
+      rc = EDD_EHIP;
+    }
+    if (graph) hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (rc) return rc;
+    std::memcpy(p->fcg_graph_key, key, sizeof key);
+  }
+  // device iteration state
+  launch_fill(p, 1, 0.0, p->scal_d + kSlotGK);
+  launch_fill(p, 1, 0.0, p->scal_d + kSlotGDone);
+  launch_fill(p, 1, tol_abs * tol_abs, p->scal_d + kSlotGTol2);
+  int k = 0, status = EDD_NOT_CONVERGED;
+  while (k < maxit) {
+    int rc = check_hip(p, hipGraphLaunch(p->fcg_graph, p->stream));
+    if (rc) return rc;
+    rc = read_scalars(p, kSlotGK, kSlotGHist + kGHist - kSlotGK);
+    if (rc) return rc;
+    k = (int)p->scal_h[kSlotGK];
+    if (st) {
+      st->precond_applications += pc_identity ? 0 : N;
+      st->lanczos_steps += pc_identity ? 0 : N * std::min(o->lanczos_kmax, 32);
+      if (!pc_identity && o->pc_form != EDD_PCF_HTILDE_FWD && o->pc_form != EDD_PCF_H_FWD)
+        st->inner_iterations += N * std::min(o->lanczos_kmax, 32) * o->inner_maxit;
+    }
+    const double rr = p->scal_h[kSlotGHist + (k - 1) % kGHist];
+    if (p->scal_h[kSlotGDone] > 0.0) {
+      *iters = (int)p->scal_h[kSlotGDone];
+      return EDD_OK;
+    }
+    if (!std::isfinite(rr) || p->scal_h[S_BREAK] != 0.0) {
+      status = EDD_EBREAKDOWN;
+      break;
+    }
+  }
+  *iters = k;
+  return status;
+}
+
 // Flexible CG on S x = rhs with S applied through interior factors of
 // precision prec; x holds the initial guess when use_guess.  Stops when the
 // recursive residual is <= tol_abs.  Returns EDD_OK, EDD_NOT_CONVERGED,
@@ -229,6 +347,11 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   const int cap = std::max(1, std::min(window, 256));
   rc = ensure_window(p, cap);
   if (rc) return rc;
+  const bool pc_dev = pc_identity || (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0);
+  if (o->use_graphs >= 2 && pc_dev && relax_abs <= 0.0 && std::sqrt(rr) > tol_abs) {
+    launch_fill(p, 1, 0.0, p->scal_d + S_BREAK);
+    return fcg_graph_iterations(p, x, prec, tol_abs, o, st, maxit, cap, iters);
+  }
   int status = EDD_OK;
   int k = 0;
   int k_switch = -1;
@@ -599,6 +722,7 @@ int edd_destroy(edd_problem *p) {
   if (!p) return EDD_OK;
   hipStreamSynchronize(p->stream);
   if (p->pc_graph) hipGraphExecDestroy(p->pc_graph);
+  if (p->fcg_graph) hipGraphExecDestroy(p->fcg_graph);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   for (void *ptr : p->allocations) {
     if (p->free_fn) p->free_fn(p->alloc_ctx, ptr);

@@ -28,6 +28,11 @@ constexpr int kCnnWidth = 32;
 // 528..1499 (kernels_pc.hip), the OC update 1536..1599 (topopt.hip), the
 // network 1600..1605 (kernels_cnn.hip), full GMRES 2048..4095 (gmres.hip).
 constexpr int kScalTotal = 4096;
+// slots of the captured interface iteration (api.hip, kernels_vec.hip):
+// iteration index k, first converged iteration + 1 (0: not yet), tol^2,
+// r.r of the step, p.q of the step, r.r history (ring of kGHist)
+constexpr int kSlotGK = 1700, kSlotGDone = 1701, kSlotGTol2 = 1702, kSlotGRR = 1703,
+              kSlotGPQ = 1704, kSlotGHist = 1708, kGHist = 256;
 __host__ __device__ inline int gamma_code(int g) { return -g - 2; }
 __host__ __device__ inline int gamma_index(int code) { return -code - 2; }
 
@@ -188,6 +193,11 @@ struct edd_problem {
   double *pc_v_d[8] = {};       // work vectors (gamma-sized)
   double *pc_h = nullptr;       // pinned host buffer for coefficients
 
+  // captured interface iterations (use_graphs >= 2)
+  hipGraphExec_t fcg_graph = nullptr;
+  int64_t fcg_graph_key[12] = {};
+  double *gr_p_d = nullptr, *gr_q_d = nullptr;  // new direction and its S product
+
   // captured preconditioner applies (device-resident form)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t pc_graph = nullptr;
@@ -332,6 +342,19 @@ void launch_window_dots(edd_problem *p, int64_t n, int m, const double *W,
 void launch_window_combine(edd_problem *p, int64_t n, int m,
                            const double *P, int cslot, int dslot,
                            const double *z, double *pv);
+// The same two steps with the window taken from the device iteration index
+// k = scal[kSlotGK] (m = min(k, cap) newest directions of the ring, oldest
+// first), so that they can run inside a captured graph: dots into
+// scal[cbase + slot], and pv = z - sum (scal[cbase+slot]/scal[dbase+slot]) P_slot.
+void launch_window_dots_dev(edd_problem *p, int64_t n, int cap, const double *W,
+                            const double *z, int cbase);
+void launch_window_combine_dev(edd_problem *p, int64_t n, int cap, const double *P,
+                               int cbase, int dbase, const double *z, double *pv);
+// ring[(k % cap) * n ...] = src
+void launch_ring_store(edd_problem *p, int64_t n, int cap, const double *src, double *ring);
+// end of a captured iteration: r.r into the history, p.q into
+// scal[pqbase + k % cap], the convergence flag, k += 1
+void launch_iter_end(edd_problem *p, int cap, int pqbase);
 // full-vector residual norms over free dofs: scal[slot] = ||f - y||^2,
 // scal[slot+1] = ||f||^2
 void launch_residual_norms(edd_problem *p, const double *f, const double *y,

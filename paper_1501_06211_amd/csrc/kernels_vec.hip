@@ -178,6 +178,138 @@ __global__ __launch_bounds__(kBlock) void k_window_dots(
   }
 }
 
+// Window dots of the captured iteration: the window is the m = min(k, cap)
+// newest directions of the ring (k = scal[kSlotGK]), age index t at ring slot
+// (first + t) % cap; partials[b*cap + t] over row chunk b, then
+// k_reduce_ring.  Same chunks and order as k_window_dots per direction.
+__global__ __launch_bounds__(kBlock) void k_window_dots_dev(
+    int64_t n, int cap, const double *__restrict__ W, const double *__restrict__ z,
+    const double *__restrict__ scal, double *__restrict__ partials) {
+  constexpr int JB = 8, NW = kBlock / 64;
+  __shared__ double red[JB][NW];
+  const int k = (int)scal[kSlotGK];
+  const int m = min(k, cap);
+  const int first = ((k - m) % cap + cap) % cap;
+  const int j0 = blockIdx.y * JB;
+  if (j0 >= m) return;  // the whole workgroup: no direction of this group yet
+  const int nj = min(JB, m - j0);
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk;
+  const int64_t hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[JB];
+#pragma unroll
+  for (int jj = 0; jj < JB; ++jj) acc[jj] = 0.0;
+  int64_t row[JB];
+#pragma unroll
+  for (int jj = 0; jj < JB; ++jj)
+    row[jj] = (int64_t)((first + j0 + (jj < nj ? jj : 0)) % cap) * n;
+  int64_t i = lo + threadIdx.x;
+  for (; i + blockDim.x < hi; i += 2 * (int64_t)blockDim.x) {
+    const int64_t i1 = i + blockDim.x;
+    const double z0 = z[i], z1 = z[i1];
+    double w0[JB], w1[JB];
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) {
+      w0[jj] = W[row[jj] + i];
+      w1[jj] = W[row[jj] + i1];
+    }
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj)
+      if (jj < nj) acc[jj] = fma(z1, w1[jj], fma(z0, w0[jj], acc[jj]));
+  }
+  if (i < hi) {
+    const double zi = z[i];
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj)
+      if (jj < nj) acc[jj] = fma(zi, W[row[jj] + i], acc[jj]);
+  }
+#pragma unroll
+  for (int jj = 0; jj < JB; ++jj) {
+    double v = acc[jj];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) red[jj][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nj) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[threadIdx.x][w];
+    partials[(int64_t)blockIdx.x * cap + j0 + threadIdx.x] = s;
+  }
+}
+
+// scal[cbase + (first + t) % cap] = sum_b partials[b*cap + t], block t < m
+__global__ __launch_bounds__(kBlock) void k_reduce_ring(const double *__restrict__ partials,
+                                                        int nblocks, int cap,
+                                                        double *__restrict__ scal, int cbase) {
+  __shared__ double red[kBlock / 64];
+  const int k = (int)scal[kSlotGK];
+  const int m = min(k, cap);
+  const int first = ((k - m) % cap + cap) % cap;
+  const int t = blockIdx.x;
+  if (t >= m) return;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    acc += partials[(int64_t)b * cap + t];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) scal[cbase + (first + t) % cap] = s;
+}
+
+// pv = z - sum over the window, oldest first, of (scal[cbase+slot] /
+// scal[dbase+slot]) P_slot: the same sequence of operations as the
+// per-segment combines of the host-driven iteration.
+__global__ __launch_bounds__(kBlock) void k_window_combine_dev(
+    int64_t n, int cap, const double *__restrict__ P, const double *__restrict__ scal,
+    int cbase, int dbase, const double *__restrict__ z, double *__restrict__ pv) {
+  __shared__ double coef[256];
+  __shared__ int64_t rows[256];
+  const int k = (int)scal[kSlotGK];
+  const int m = min(k, cap);
+  const int first = ((k - m) % cap + cap) % cap;
+  for (int t = threadIdx.x; t < m; t += blockDim.x) {
+    const int slot = (first + t) % cap;
+    coef[t] = scal[cbase + slot] / scal[dbase + slot];
+    rows[t] = (int64_t)slot * n;
+  }
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = z[i];
+    int j = 0;
+    for (; j + 4 <= m; j += 4) {
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = P[rows[j + u] + i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v = fma(-coef[j + u], a[u], v);
+    }
+    for (; j < m; ++j) v = fma(-coef[j], P[rows[j] + i], v);
+    pv[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ring_store(int64_t n, int cap,
+                                                       const double *__restrict__ scal,
+                                                       const double *__restrict__ src,
+                                                       double *__restrict__ ring) {
+  const int64_t slot = (int64_t)((int)scal[kSlotGK] % cap);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    ring[slot * n + i] = src[i];
+}
+
+__global__ void k_iter_end(double *__restrict__ scal, int cap, int pqbase) {
+  if (threadIdx.x != 0) return;
+  const int k = (int)scal[kSlotGK];
+  const double rr = scal[kSlotGRR];
+  scal[pqbase + k % cap] = scal[kSlotGPQ];
+  scal[kSlotGHist + k % kGHist] = rr;
+  if (scal[kSlotGDone] == 0.0 && rr <= scal[kSlotGTol2]) scal[kSlotGDone] = k + 1;
+  scal[kSlotGK] = k + 1;
+}
+
 // pv = z - sum_j (scal[cslot+j] / scal[dslot+j]) P_j  (m <= 256)
 __global__ __launch_bounds__(kBlock) void k_window_combine(
     int64_t n, int m, const double *__restrict__ P,
@@ -291,6 +423,29 @@ void launch_window_combine(edd_problem *p, int64_t n, int m, const double *P,
                            int cslot, int dslot, const double *z, double *pv) {
   k_window_combine<<<grid_for(n), kBlock, 0, p->stream>>>(n, m, P, p->scal_d,
                                                           cslot, dslot, z, pv);
+}
+
+void launch_window_dots_dev(edd_problem *p, int64_t n, int cap, const double *W,
+                            const double *z, int cbase) {
+  unsigned g = grid_for(n);
+  if (g > 256) g = 256;
+  k_window_dots_dev<<<dim3(g, (cap + 7) / 8), kBlock, 0, p->stream>>>(n, cap, W, z, p->scal_d,
+                                                                     p->partials_d);
+  k_reduce_ring<<<cap, kBlock, 0, p->stream>>>(p->partials_d, (int)g, cap, p->scal_d, cbase);
+}
+
+void launch_window_combine_dev(edd_problem *p, int64_t n, int cap, const double *P,
+                               int cbase, int dbase, const double *z, double *pv) {
+  k_window_combine_dev<<<grid_for(n), kBlock, 0, p->stream>>>(n, cap, P, p->scal_d, cbase,
+                                                              dbase, z, pv);
+}
+
+void launch_ring_store(edd_problem *p, int64_t n, int cap, const double *src, double *ring) {
+  k_ring_store<<<grid_for(n), kBlock, 0, p->stream>>>(n, cap, p->scal_d, src, ring);
+}
+
+void launch_iter_end(edd_problem *p, int cap, int pqbase) {
+  k_iter_end<<<1, 64, 0, p->stream>>>(p->scal_d, cap, pqbase);
 }
 
 void launch_residual_norms(edd_problem *p, const double *f, const double *y,

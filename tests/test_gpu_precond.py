@@ -297,3 +297,41 @@ def test_h_theta_on_a_skeleton_away_from_the_clamp():
     uref = fe.solve_direct(p)
     assert np.linalg.norm(to_np(u) - uref) <= 1e-8 * np.linalg.norm(uref)
     prob.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("precond", ["identity", "htheta"])
+def test_captured_iteration_graph(dim, precond):
+    """use_graphs = n >= 2: the interface iterations replayed from a captured
+    graph of n iterations (window position from the device iteration index,
+    device convergence flag).  Up to convergence the arithmetic is that of
+    the host-driven loop, so the iteration counts agree; the steps a replay
+    runs after convergence refine u (the host loop runs up to 3 such steps,
+    a replay up to n-1), so the solutions agree to the solver tolerance, and
+    where the FP64 true-residual check restarts the iteration (near the
+    floor) the counts may differ by a replay or two.
+    Replays on one handle are bitwise repeatable."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _small2d() if dim == 2 else _small3d()
+    pc = edd.PC_IDENTITY if precond == "identity" else edd.PC_HTHETA
+    prob = make_problem(p)
+    f = to_cuda(p.f)
+    uref = fe.solve_direct(p)
+    u0, s0 = prob.solve(f, tol=1e-10, maxit=3000, precond=pc)
+    u0 = to_np(u0)
+    for n in (8, 5):
+        outs = []
+        for rep in range(2):
+            u1, s1 = prob.solve(f, tol=1e-10, maxit=3000, precond=pc, use_graphs=n)
+            outs.append(to_np(u1))
+            print(f"{dim}D {precond} graph of {n}: its {s1['iterations']} (host loop "
+                  f"{s0['iterations']}), flags {s1['flags']}")
+            # equal unless an FP64 true-residual restart (near the floor) falls
+            # differently: then within two replays
+            assert abs(s1["iterations"] - s0["iterations"]) <= 2 * n
+            assert s1["rel_residual"] <= 1e-10
+        assert np.array_equal(outs[0], outs[1])
+        assert np.linalg.norm(outs[0] - u0) <= 1e-9 * np.linalg.norm(u0)
+        assert np.linalg.norm(outs[0] - uref) <= 1e-8 * np.linalg.norm(uref)
+    prob.close()
