@@ -517,6 +517,8 @@ LEG_OPTS = {
     "mixed": ("f64+f32", {"mixed": True}),
     "learned": ("f64", {"learned_guess": 1}),
     "learned_mixed": ("f64+f32", {"mixed": True, "learned_guess": 1}),
+    # the network also as the direction of every 10th interface step
+    "learned_corr": ("f64", {"learned_guess": 1, "learned_correction": 10}),
 }
 
 
@@ -527,6 +529,8 @@ def leg_opts(leg, args):
                    args.switch, args.graphs)
     if extra.get("learned_guess"):
         o["learned_guess"] = 1
+    if extra.get("learned_correction"):
+        o["learned_correction"] = extra["learned_correction"]
     return o
 
 

@@ -91,7 +91,7 @@ extern "C" {
 #define EDD_FLAG_MIXED_FALLBACK 2   /* mixed path stalled; fell back to FP64   */
 #define EDD_FLAG_PC_DROPPED 4       /* reserved: never set (a step without     */
                                     /* descent ends the solve, EDD_EBREAKDOWN) */
-#define EDD_FLAG_LEARNED_REJECTED 8 /* the network's proposal was dropped: its */
+#define EDD_FLAG_LEARNED_REJECTED 8 /* a network proposal was dropped: its      */
                                     /* interface energy <d,Sd> was not positive */
 
 typedef struct edd_problem edd_problem;
@@ -170,6 +170,12 @@ typedef struct edd_solve_opts {
                       /* refine u.  Kernel timing is not recorded inside the */
                       /* graph.                                              */
   int pc_form;        /* EDD_PCF_*: which interface norm S~ applies and how  */
+  int learned_correction; /* K > 0: every K-th interface step takes its      */
+                      /* direction from the correction network applied to the */
+                      /* interface residual extended by zero instead of S~;   */
+                      /* a step without a usable direction is dropped (flag   */
+                      /* EDD_FLAG_LEARNED_REJECTED); needs edd_cnn_setup;     */
+                      /* 0: off                                               */
 } edd_solve_opts;
 
 typedef struct edd_solve_stats {

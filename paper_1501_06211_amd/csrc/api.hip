@@ -45,6 +45,7 @@ enum : int {
   S_BAD = 7,
   S_BREAK = 8,  // set on the device by a breakdown step of the interface CG
   S_RRH = 9,    // 9..12: r.r of the last iterations (ring of kCheck)
+  S_NETDROP = 13,  // set by a network step that gave no direction (dropped)
   S_C_BASE = 16,
   S_PQ_BASE = 16 + 256,
   S_PC_BASE = 16 + 512,
@@ -348,7 +349,8 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   rc = ensure_window(p, cap);
   if (rc) return rc;
   const bool pc_dev = pc_identity || (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0);
-  if (o->use_graphs >= 2 && pc_dev && relax_abs <= 0.0 && std::sqrt(rr) > tol_abs) {
+  if (o->use_graphs >= 2 && pc_dev && relax_abs <= 0.0 && o->learned_correction <= 0 &&
+      std::sqrt(rr) > tol_abs) {
     launch_fill(p, 1, 0.0, p->scal_d + S_BREAK);
     return fcg_graph_iterations(p, x, prec, tol_abs, o, st, maxit, cap, iters);
   }
@@ -363,6 +365,7 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   const bool pc_device = pc_identity || (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0);
   const int check = pc_device ? kCheck : 1;
   launch_fill(p, 1, 0.0, p->scal_d + S_BREAK);
+  launch_fill(p, 1, 0.0, p->scal_d + S_NETDROP);
   int converged_at = -1;
   while (std::sqrt(rr) > tol_abs) {
     if (k >= maxit) { status = EDD_NOT_CONVERGED; break; }
@@ -381,7 +384,23 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
       rr_switch = rr;
     }
     const double *zp = r;
-    if (!pc_identity) {
+    int flag_slot = S_BREAK;
+    // every learned_correction-th step takes its direction from the
+    // correction network applied to the interface residual extended by zero
+    // (an approximation of S^{-1} r = (K^{-1} [0; r])_G): the flexible
+    // iteration accepts a different preconditioner at every step, and the
+    // exact line search keeps the step from raising the energy error; a
+    // network step with no usable direction is dropped
+    const bool net_step = o->learned_correction > 0 && p->cnn_nparams > 0 && k > 0 &&
+                          k % o->learned_correction == 0;
+    if (net_step) {
+      launch_scatter_solution(p, nullptr, r, p->cnn_r_d);
+      rc = cnn_predict(p, nullptr, p->cnn_r_d, p->cnn_dir_d);
+      if (rc) return rc;
+      launch_gather(p, p->gnode_d, p->n_gamma, p->cnn_dir_d, z);
+      zp = z;
+      flag_slot = S_NETDROP;
+    } else if (!pc_identity) {
       rc = precond_apply(p, r, z, o, st, prec == EDD_F32);
       if (rc) return rc;
       zp = z;
@@ -398,7 +417,7 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
       launch_dots(p, nG, 2, a, b, S_PQCUR);
     }
     launch_cg_update(p, nG, S_PR, S_PQCUR, x, Pk, r, Qk, S_RRH + (k % kCheck),
-                     S_PQ_BASE + slot, S_BREAK);
+                     S_PQ_BASE + slot, flag_slot);
     ++k;
     if (k % check != 0 && k < maxit) continue;
     rc = read_scalars(p, 0, S_RRH + kCheck);
@@ -423,6 +442,11 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
     }
   }
   *iters = converged_at >= 0 ? converged_at : k;
+  if (o->learned_correction > 0 && st) {
+    int rc2 = read_scalars(p, S_NETDROP, 1);
+    if (rc2) return rc2;
+    if (p->scal_h[S_NETDROP] != 0.0) st->flags |= EDD_FLAG_LEARNED_REJECTED;
+  }
   return status;
 }
 
@@ -700,6 +724,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->learned_guess = 0;
   o->use_graphs = 0;
   o->pc_form = EDD_PCF_HTILDE_INV;
+  o->learned_correction = 0;
 }
 
 const char *edd_strerror(int code) {
@@ -1337,6 +1362,8 @@ int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
   if (rc) return rc;
   if (!std::isfinite(nf)) return EDD_EINVAL;
   int status = EDD_OK;
+  if (o.learned_correction < 0) return EDD_EINVAL;
+  if (o.learned_correction > 0 && !p->cnn_nparams) return EDD_ESTATE;
   if (o.learned_guess && nf > 0.0) {
     if (!p->cnn_nparams) return EDD_ESTATE;
     rc = learned_guess(p, f_dev, u_dev, &o, &st);

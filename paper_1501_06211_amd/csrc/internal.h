@@ -272,6 +272,8 @@ void launch_apply_mapped(edd_problem *p, const int *tgt, int64_t ntgt,
 void launch_assemble_band(edd_problem *p);
 void launch_gather(edd_problem *p, const int *nodes, int64_t n,
                    const double *full, double *packed);
+// u = (uI, uG) as a full nodal vector, zero on clamped dofs; uI may be
+// null (interior entries zero)
 void launch_scatter_solution(edd_problem *p, const double *uI,
                              const double *uG, double *u);
 void launch_check_moduli(edd_problem *p, const double *E, double *flag);

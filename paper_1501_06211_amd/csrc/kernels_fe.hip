@@ -393,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_solution(
   const int c = (int)(t - node * dim);
   const int code = nmap[node];
   double v = 0.0;
-  if (code >= 0) v = uI[code + c];
+  if (code >= 0) v = uI ? uI[code + c] : 0.0;
   else if (code != kDirichlet) v = uG[(int64_t)dim * gamma_index(code) + c];
   u[t] = v;
 }

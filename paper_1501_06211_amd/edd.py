@@ -84,6 +84,7 @@ class SolveOpts(ctypes.Structure):
         ("learned_guess", ctypes.c_int),
         ("use_graphs", ctypes.c_int),
         ("pc_form", ctypes.c_int),
+        ("learned_correction", ctypes.c_int),
     ]
 
 

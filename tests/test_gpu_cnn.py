@@ -171,3 +171,30 @@ def test_trained_network_gain_on_a_sequence():
     assert hist[-1] < hist[0]
     assert r1.mean() < r0.mean()
     prob.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_network_steps_inside_the_flexible_iteration(dim):
+    """learned_correction = K: every K-th interface step takes the network's
+    proposal for the interface residual (extended by zero) as its direction.
+    The flexible iteration's exact line search keeps such steps safe: with
+    random weights the solution still matches the direct solve; with all-zero
+    weights every network step is dropped (flagged) and the other steps are
+    those of the plain iteration."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p, r, e, params = _case(dim)
+    prob = _gpu(p, params)
+    uref = fe.solve_direct(p)
+    f = to_cuda(p.f)
+    u0, s0 = prob.solve(f, tol=1e-11, maxit=4000)
+    u1, s1 = prob.solve(f, tol=1e-11, maxit=4000, learned_correction=5)
+    err = _rel(to_np(u1), uref)
+    print(f"{dim}D network steps every 5: its {s1['iterations']} (plain {s0['iterations']}), "
+          f"u_err {err:.1e}, flags {s1['flags']}")
+    assert err <= 1e-8
+    prob.cnn_set_params(torch.zeros(prob.cnn_setup(32), dtype=torch.float32, device="cuda"))
+    u2, s2 = prob.solve(f, tol=1e-11, maxit=4000, learned_correction=5)
+    assert s2["flags"] & edd.FLAG_LEARNED_REJECTED
+    assert _rel(to_np(u2), uref) <= 1e-8
+    prob.close()
