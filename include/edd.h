@@ -376,6 +376,12 @@ int edd_set_apply_variant(edd_problem *p, int variant);
 /* Allocate the network for this problem; width must be 32.  Parameters
  * start at zero. */
 int edd_cnn_setup(edd_problem *p, int width);
+/* 1: run the forward pass of the two hidden 32 -> 32 layers on the FP16
+ * matrix cores (implicit GEMM by v_mfma_f32_16x16x16_f16: FP16 weights and
+ * FP16-rounded activations, FP32 accumulation; relative error against the
+ * FP32 path about 1e-3), for inference and training alike; 0 (default):
+ * the FP32 vector path.  Needs edd_cnn_setup. */
+int edd_cnn_matrix_cores(edd_problem *p, int enable);
 /* Number of FP32 parameters. */
 int edd_cnn_num_params(edd_problem *p, int64_t *n);
 /* Copy device parameters in (resets the Adam moments) or out. */

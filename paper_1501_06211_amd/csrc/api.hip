@@ -1282,6 +1282,13 @@ int edd_cnn_setup(edd_problem *p, int width) {
   return EDD_OK;
 }
 
+int edd_cnn_matrix_cores(edd_problem *p, int enable) {
+  if (!p) return EDD_EINVAL;
+  if (!p->cnn_nparams) return EDD_ESTATE;
+  p->cnn_matrix_cores = enable ? 1 : 0;
+  return EDD_OK;
+}
+
 int edd_cnn_num_params(edd_problem *p, int64_t *n) {
   if (!p || !n) return EDD_EINVAL;
   if (!p->cnn_nparams) return EDD_ESTATE;

@@ -227,6 +227,7 @@ struct edd_problem {
   int64_t cnn_nparams = 0;
   int64_t cnn_off[edd::kCnnLayers] = {};
   int cnn_t = 0;           // Adam steps taken
+  int cnn_matrix_cores = 0;  // hidden layers' forward on the FP16 matrix cores
   double cnn_nfree = 0.0;  // free dofs (rms normalisation)
   float *cnn_master_d = nullptr, *cnn_m_d = nullptr, *cnn_v_d = nullptr,
         *cnn_grad_d = nullptr, *cnn_part_d = nullptr, *cnn_target_d = nullptr;

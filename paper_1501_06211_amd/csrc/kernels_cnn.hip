@@ -13,6 +13,8 @@
 // fixed node chunks and then over chunks in a fixed order (deterministic).
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace edd {
@@ -157,6 +159,79 @@ __global__ __launch_bounds__(kCnnNT) void k_conv_fwd(NodeGrid g, int64_t nn, int
   float *y = out + n * CO;
 #pragma unroll
   for (int o = 0; o < CO; ++o) y[o] = RELU ? fmaxf(acc[o], 0.0f) : acc[o];
+}
+
+// The hidden 32 -> 32 layers on the FP16 matrix cores: an implicit GEMM per
+// wavefront over 16 nodes (M), the 32 outputs (two 16-column N tiles) and
+// K = taps x 32 input channels in chunks of 16, by v_mfma_f32_16x16x16_f16
+// with FP32 accumulation.  Lane l supplies A[l%16][4(l/16)+j] (node l%16 of
+// the tile, four input channels of the chunk from its tap neighbour,
+// rounded to FP16) and B[4(l/16)+j][l%16] (the FP16 weights, staged in LDS
+// transposed per tap so that the four values are contiguous), and holds
+// D[4(l/16)+e][l%16] (layout checked on the device).  Activations rounded to
+// FP16 add a relative error of about 1e-3 against the FP32 path.
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+template <int D, bool RELU>
+__global__ __launch_bounds__(256) void k_conv_fwd_mfma(NodeGrid g, int64_t nn, int s,
+                                                       const __half *__restrict__ w,
+                                                       const float *__restrict__ in,
+                                                       float *__restrict__ out) {
+  constexpr int NTAP = ntaps<D>();
+  constexpr int C = kCnnWidth;
+  static_assert(C == 32, "the matrix-core layer is written for 32 channels");
+  __shared__ _Float16 Wt[NTAP * C * C];
+  __shared__ float bs[C];
+  for (int k = threadIdx.x; k < NTAP * C * C; k += blockDim.x) {
+    const int t = k / (C * C), i = (k / C) % C, o = k % C;
+    Wt[(t * C + o) * C + i] = (_Float16)__half2float(w[k]);
+  }
+  for (int o = threadIdx.x; o < C; o += blockDim.x) bs[o] = __half2float(w[NTAP * C * C + o]);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lm = lane % 16, lk = 4 * (lane / 16);
+  const int64_t ntiles = (nn + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+    const int64_t na = tile * 16 + lm;  // the node whose A row this lane supplies
+    int c[3] = {0, 0, 0};
+    const bool valid = na < nn;
+    if (valid) node_coords<D>(g, na, c);
+    float4_t acc0, acc1;
+    for (int e = 0; e < 4; ++e) {
+      acc0[e] = bs[lm];
+      acc1[e] = bs[16 + lm];
+    }
+    for (int t = 0; t < NTAP; ++t) {
+      const int64_t m = valid ? tap_neighbour<D>(g, c, t, s, 1) : -1;
+#pragma unroll
+      for (int kc = 0; kc < C / 16; ++kc) {
+        const int ch = kc * 16 + lk;
+        half4_t a;
+        if (m >= 0) {
+          const float4 xv = *reinterpret_cast<const float4 *>(in + m * C + ch);
+          a[0] = (_Float16)xv.x;
+          a[1] = (_Float16)xv.y;
+          a[2] = (_Float16)xv.z;
+          a[3] = (_Float16)xv.w;
+        } else {
+          a[0] = a[1] = a[2] = a[3] = (_Float16)0.0f;
+        }
+        const half4_t b0 = *reinterpret_cast<const half4_t *>(&Wt[(t * C + lm) * C + ch]);
+        const half4_t b1 = *reinterpret_cast<const half4_t *>(&Wt[(t * C + 16 + lm) * C + ch]);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b1, acc1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t node = tile * 16 + lk + e;
+      if (node < nn) {
+        out[node * C + lm] = RELU ? fmaxf(acc0[e], 0.0f) : acc0[e];
+        out[node * C + 16 + lm] = RELU ? fmaxf(acc1[e], 0.0f) : acc1[e];
+      }
+    }
+  }
 }
 
 // the same weights transposed per tap, Wt[t][o][i], for the backward pass
@@ -373,6 +448,13 @@ struct Net {
 
   template <int CI, int CO, bool RELU>
   static void fwd(edd_problem *p, int layer, const float *in, float *out) {
+    if (CI == kCnnWidth && CO == kCnnWidth && p->cnn_matrix_cores) {
+      const int64_t ntiles = (p->n_nodes + 15) / 16;
+      const unsigned nb = (unsigned)std::min<int64_t>((ntiles + 3) / 4, 4096);
+      k_conv_fwd_mfma<D, RELU><<<nb, 256, 0, p->stream>>>(
+          node_grid(p), p->n_nodes, kCnnDil[layer], p->cnn_w16_d + p->cnn_off[layer], in, out);
+      return;
+    }
     const auto k = k_conv_fwd<D, CI, CO, RELU>;
     const size_t sh = lds(CI, CO);
     hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);

@@ -39,6 +39,7 @@ EXPORTS = [
     "edd_set_solve_variants", "edd_apply_S_noalloc", "edd_cnn_training_pair",
     "edd_element_energies", "edd_oc_update", "edd_default_topopt_opts", "edd_topopt_run",
     "edd_solve_gmres", "edd_autotune_cache", "edd_set_apply_variant",
+    "edd_cnn_matrix_cores",
 ]
 NOALLOC_MAX_INTERIOR_DOFS = 1 << 21
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
@@ -219,6 +220,7 @@ def lib():
     L.edd_set_apply_variant.argtypes = [vp, i32]
     L.edd_set_solve_variants.argtypes = [vp, ctypes.POINTER(i32)]
     L.edd_cnn_setup.argtypes = [vp, i32]
+    L.edd_cnn_matrix_cores.argtypes = [vp, i32]
     L.edd_cnn_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.edd_cnn_set_params.argtypes = [vp, vp]
     L.edd_cnn_get_params.argtypes = [vp, vp]
@@ -444,6 +446,10 @@ class Problem:
         with self._ordered():
             self._check(lib().edd_cnn_setup(self.h, width), "edd_cnn_setup")
         return self._nparams()
+
+    def cnn_matrix_cores(self, enable=True):
+        """Hidden layers' forward pass on the FP16 matrix cores (edd_cnn_matrix_cores)."""
+        self._check(lib().edd_cnn_matrix_cores(self.h, int(enable)), "edd_cnn_matrix_cores")
 
     def cnn_set_params(self, params: torch.Tensor):
         pp = self._v(params, self._nparams(), "params", torch.float32)

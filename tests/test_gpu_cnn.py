@@ -198,3 +198,27 @@ def test_network_steps_inside_the_flexible_iteration(dim):
     assert s2["flags"] & edd.FLAG_LEARNED_REJECTED
     assert _rel(to_np(u2), uref) <= 1e-8
     prob.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_matrix_core_forward(dim):
+    """edd_cnn_matrix_cores: the hidden 32 -> 32 layers as implicit GEMMs on
+    the FP16 matrix cores (FP16 weights and activations, FP32 accumulation).
+    Against the FP64 oracle with the same FP16 weights the relative error is
+    that of FP16 activations (bound 1e-2, printed); training through it still
+    lowers the loss."""
+    require_gpu()
+    p, r, e, params = _case(dim)
+    prob = _gpu(p, params)
+    d32 = to_np(prob.cnn_predict(to_cuda(r)))
+    prob.cnn_matrix_cores(True)
+    d16 = to_np(prob.cnn_predict(to_cuda(r)))
+    ref = cnn.predict(cnn.round_fp16(params), p, r)
+    err, err32 = _rel(d16, ref), _rel(d16, d32)
+    print(f"{dim}D matrix-core forward: relative error vs FP64 oracle {err:.2e}, "
+          f"vs the FP32 path {err32:.2e}")
+    assert err < 1e-2
+    assert np.array_equal(d16, to_np(prob.cnn_predict(to_cuda(r))))  # deterministic
+    losses = [prob.cnn_train_step(to_cuda(r), to_cuda(e), lr=1e-3) for _ in range(20)]
+    assert losses[-1] < losses[0]
+    prob.close()
