@@ -89,7 +89,7 @@ def parse():
                          "once the interface residual has dropped by --switch), learned "
                          "(FP64 with the network's line-searched initial guess), "
                          "learned_mixed (both)")
-    ap.add_argument("--switch", type=float, default=1e-3,
+    ap.add_argument("--switch", type=float, default=1e-2,
                     help="mixed legs: relative interface residual at which the "
                          "S applies move to FP32 factors")
     ap.add_argument("--train-fields", type=int, default=8,
