@@ -328,13 +328,15 @@ int edd_solve_batch(edd_problem *const *ps, int n, const double *const *f_dev,
                     double *const *u_dev, const edd_solve_opts *o,
                     edd_solve_stats *stats, int nthreads);
 
-/* Autotuner of the tile shapes (the benchmark spec's project-written tuner):
+/* Autotuner of the tile shapes:
  *  - the batched interior substitution: every variant valid for this
  *    problem's bands (1-3: one row per thread with an owner wavefront per
  *    diagonal block, 64/256/512 threads per subdomain; 4-6: wide bands, a
  *    dedicated chain wavefront and 1024 threads, two load chunk widths, the
- *    narrower one also double-buffered), for FP64 and (if present) FP32
- *    factors, timed on the current factors;
+ *    narrower one also double-buffered; 7: as 6 with lookahead, the chain
+ *    wavefront applying the previous block to its own rows while the others
+ *    apply it to the rows below), for FP64 and (if present) FP32 factors,
+ *    timed on the current factors;
  *  - the element kernel: node tiles of 16x16 / 32x8 / 64x4 (2D) or 8x8x4 /
  *    16x4x4 / 16x8x2 (3D) nodes (every shape gives bitwise the same result),
  *    chosen separately for the full product, the product on interior nodes

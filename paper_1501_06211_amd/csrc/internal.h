@@ -289,7 +289,7 @@ void launch_band_layouts(edd_problem *p);
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x);
 bool band_solve_variant_ok(const edd_problem *p, int v);
-constexpr int kBandSolveVariants = 6;
+constexpr int kBandSolveVariants = 7;
 constexpr int kApplyVariants = 3;  // node-tile shapes of the element kernel
 
 // kernels_vec.hip

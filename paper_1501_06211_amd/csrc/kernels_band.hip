@@ -397,6 +397,236 @@ __global__ __launch_bounds__(kWideNT) void k_band_solve_wide(
   for (int i = tid; i < n; i += kWideNT) x[s.dof_off + i] = (double)xs[i];
 }
 
+// ---------------------------------------------------------------------------
+// Wide bands with lookahead.  As k_band_solve_wide, but the chain wavefront
+// also applies the previous block to its own 64 rows (the 64 x 64 block
+// below it, with the previous block's solution held in its registers), and
+// the other wavefronts apply the previous block to the rows beyond.  Then a
+// step has one barrier and the chain's triangular solve overlaps the
+// off-diagonal stream instead of alternating with it.
+//   forward, step bk (j0 = 64 bk, jp = j0 - 64): the chain applies columns
+//     jp.. to rows j0..j0+63, then solves block bk; helper t' applies
+//     columns jp.. to row jp + 128 + t' (t' < kd - 64);
+//   backward, step bk (jn = j0 + 64): the chain applies rows jn.. of L (the
+//     solution of block bk+1) to unknowns j0..j0+63, then solves block bk;
+//     helper t applies them to unknown jn - kd + t (t < kd - 64).
+// Every (row block, column block) pair is applied once: the adjacent pair
+// by the chain, the rest by the helpers one step earlier, before the barrier
+// that the chain's next read follows.
+// ---------------------------------------------------------------------------
+template <typename T, typename W, int CW>
+__global__ __launch_bounds__(kWideNT) void k_band_solve_la(
+    const SubDesc *__restrict__ subs, const int *__restrict__ order,
+    const T *__restrict__ Cs, const T *__restrict__ Rs, int64_t fac_len, int phase,
+    const double *__restrict__ b, double *__restrict__ x) {
+  constexpr int NB = 64, NCH = NB / CW;
+  static_assert(NB % CW == 0 && NCH % 2 == 0, "chunks tile the block, buffers alternate");
+  extern __shared__ __align__(16) unsigned char smem[];
+  W *xs = reinterpret_cast<W *>(smem);
+  const SubDesc s = subs[order[blockIdx.x]];
+  const int n = s.n, np = s.np, kd = s.kd, ld = kd + 1;
+  const __amdgpu_buffer_rsrc_t Cr = band_rsrc(Cs + s.fac_off, fac_len - s.fac_off);
+  const __amdgpu_buffer_rsrc_t Rr = band_rsrc(Rs + s.fac_off, fac_len - s.fac_off);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const bool chainw = tid < 64;
+  const int u = tid - 64;  // helper index
+  const int nblk = np / NB;
+
+  for (int i = tid; i < np; i += kWideNT) xs[i] = i < n ? (W)b[s.dof_off + i] : (W)0;
+  T buf[2][CW];
+
+  // ---- forward: L y = b, column layout (i, j) at C[j*kd + i] ----
+  if (phase != 2) {
+    W yprev = 0;
+    if (chainw) load_cols<T, CW>(buf[0], Cr, lane, kd, 0);
+    __syncthreads();
+    for (int bk = 0; bk < nblk; ++bk) {
+      const int j0 = bk * NB;
+      const int64_t jb = (int64_t)j0 * ld, jpb = jb - (int64_t)NB * ld;
+      if (chainw) {
+        W xi = xs[j0 + lane];
+        if (bk > 0) {
+          // (j0+lane, jp+c) at jpb + c*kd + 64 + lane, in the band iff
+          // 64 + lane - c <= kd; the last chunk's request is the diagonal
+          // block's first
+          const int cmin = NB + lane - kd;
+          W a0 = 0, a1 = 0;
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) {
+            T(&cur)[CW] = buf[h & 1];
+            if (h + 1 < NCH) load_cols<T, CW>(buf[(h + 1) & 1], Cr, jpb + NB + lane, kd, (h + 1) * CW);
+            else load_cols<T, CW>(buf[(h + 1) & 1], Cr, jb + lane, kd, 0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int cc = 0; cc < CW; cc += 2) {
+              const int c = h * CW + cc;
+              a0 = fma(c >= cmin ? (W)cur[cc] : (W)0, lane_bcast(yprev, c), a0);
+              a1 = fma(c + 1 >= cmin ? (W)cur[cc + 1] : (W)0, lane_bcast(yprev, c + 1), a1);
+            }
+          }
+          xi -= a0 + a1;
+        }
+        W dd = 0;
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) {
+          T(&cur)[CW] = buf[h & 1];
+          if (h + 1 < NCH) load_cols<T, CW>(buf[(h + 1) & 1], Cr, jb + lane, kd, (h + 1) * CW);
+          else if (bk + 1 < nblk) load_cols<T, CW>(buf[(h + 1) & 1], Cr, jb + NB + lane, kd, 0);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int cc = 0; cc < CW; ++cc) {
+            const int c = h * CW + cc;
+            dd = (c == lane) ? (W)cur[cc] : dd;
+            cur[cc] = (c < lane && lane - c <= kd) ? cur[cc] : (T)0;
+          }
+#pragma unroll
+          for (int cc = 0; cc < CW; ++cc) {
+            const int c = h * CW + cc;
+            const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
+            xi = fma(-(W)cur[cc], yc, xi);
+          }
+        }
+        yprev = xi * dd;
+        xs[j0 + lane] = yprev;
+      } else if (bk > 0) {
+        // row jp + off, columns jp + c: (jp+c)*kd + jp + off, in the band
+        // iff off - c <= kd
+        const int jp = j0 - NB;
+        const int off = 2 * NB + u;
+        const int i = jp + off;
+        if (off - (NB - 1) <= kd && i < np) {
+          const int cmin = off - kd;
+          W a0 = 0, a1 = 0;
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) {
+            T(&cur)[CW] = buf[h & 1];
+            if (h + 1 < NCH) load_cols<T, CW>(buf[(h + 1) & 1], Cr, jpb + off, kd, (h + 1) * CW);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int cc = 0; cc < CW; cc += 2) {
+              const int c = h * CW + cc;
+              a0 = fma(c >= cmin ? (W)cur[cc] : (W)0, xs[jp + c], a0);
+              a1 = fma(c + 1 >= cmin ? (W)cur[cc + 1] : (W)0, xs[jp + c + 1], a1);
+            }
+          }
+          xs[i] -= a0 + a1;
+        }
+      }
+      // the helpers' first chunk of step bk+1 (block bk's columns)
+      if (!chainw && bk + 1 < nblk) {
+        const int off = 2 * NB + u;
+        if (off - (NB - 1) <= kd && j0 + off < np) load_cols<T, CW>(buf[0], Cr, jb + off, kd, 0);
+      }
+      __syncthreads();
+    }
+  }
+  if (phase == 1) {
+    for (int i = tid; i < n; i += kWideNT) x[s.dof_off + i] = (double)xs[i];
+    return;
+  }
+
+  // ---- backward: L^T x = y, row layout (i, j) at R[i*ld + (i - j)] ----
+  __syncthreads();
+  {
+    W xprev = 0;
+    if (chainw) load_cols<T, CW>(buf[0], Rr, (int64_t)(nblk - 1) * NB * ld - lane, ld + 1, NB - CW);
+    __syncthreads();
+    for (int bk = nblk - 1; bk >= 0; --bk) {
+      const int j0 = bk * NB;
+      const int64_t jb = (int64_t)j0 * ld, jnb = jb + (int64_t)NB * ld;
+      if (chainw) {
+        W xi = xs[j0 + lane];
+        if (bk + 1 < nblk) {
+          // (jn+c, j0+lane) at jnb + c*(ld+1) + 64 - lane, in the band iff
+          // 64 + c - lane <= kd; the last chunk's request is the diagonal
+          // block's first (its last columns)
+          const int cmax = kd - NB + lane;
+          W a0 = 0, a1 = 0;
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) {
+            T(&cur)[CW] = buf[h & 1];
+            if (h + 1 < NCH) load_cols<T, CW>(buf[(h + 1) & 1], Rr, jnb + NB - lane, ld + 1, (h + 1) * CW);
+            else load_cols<T, CW>(buf[(h + 1) & 1], Rr, jb - lane, ld + 1, NB - CW);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int cc = 0; cc < CW; cc += 2) {
+              const int c = h * CW + cc;
+              a0 = fma(c <= cmax ? (W)cur[cc] : (W)0, lane_bcast(xprev, c), a0);
+              a1 = fma(c + 1 <= cmax ? (W)cur[cc + 1] : (W)0, lane_bcast(xprev, c + 1), a1);
+            }
+          }
+          xi -= a0 + a1;
+        }
+        // diagonal block, chunks from the last columns down (the order of
+        // the triangular solve); chain lane i reads (j0+c, j0+i) at
+        // jb + c*(ld+1) - i
+        W dd = 0;
+#pragma unroll
+        for (int st = 0; st < NCH; ++st) {
+          const int h = NCH - 1 - st;
+          T(&cur)[CW] = buf[st & 1];
+          if (st + 1 < NCH) load_cols<T, CW>(buf[(st + 1) & 1], Rr, jb - lane, ld + 1, (h - 1) * CW);
+          else if (bk > 0) load_cols<T, CW>(buf[(st + 1) & 1], Rr, jb + NB - lane, ld + 1, 0);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int cc = 0; cc < CW; ++cc) {
+            const int c = h * CW + cc;
+            dd = (c == lane) ? (W)cur[cc] : dd;
+            cur[cc] = (c > lane && c - lane <= kd) ? cur[cc] : (T)0;
+          }
+#pragma unroll
+          for (int cc = CW - 1; cc >= 0; --cc) {
+            const int c = h * CW + cc;
+            const W yc = lane_bcast(xi, c) * lane_bcast(dd, c);
+            xi = fma(-(W)cur[cc], yc, xi);
+          }
+        }
+        xprev = xi * dd;
+        xs[j0 + lane] = xprev;
+      } else if (bk + 1 < nblk) {
+        // unknown i = jn - kd + t < j0, rows jn + c of L: (jn+c)*ld +
+        // (jn + c - i) = jnb + c*(ld+1) + (kd - t), in the band iff c <= t
+        const int jn = j0 + NB;
+        const int t = u;
+        const int i = jn - kd + t;
+        if (t < kd - NB && i >= 0) {
+          W a0 = 0, a1 = 0;
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) {
+            T(&cur)[CW] = buf[h & 1];
+            if (h + 1 < NCH) load_cols<T, CW>(buf[(h + 1) & 1], Rr, jnb + (kd - t), ld + 1, (h + 1) * CW);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int cc = 0; cc < CW; cc += 2) {
+              const int c = h * CW + cc;
+              a0 = fma(c <= t ? (W)cur[cc] : (W)0, xs[jn + c], a0);
+              a1 = fma(c + 1 <= t ? (W)cur[cc + 1] : (W)0, xs[jn + c + 1], a1);
+            }
+          }
+          xs[i] -= a0 + a1;
+        }
+      }
+      // the helpers' first chunk of step bk-1 (block bk's rows of L)
+      if (!chainw && bk > 0) {
+        const int t = u;
+        if (t < kd - NB && j0 - kd + t >= 0) load_cols<T, CW>(buf[0], Rr, jb + (kd - t), ld + 1, 0);
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < n; i += kWideNT) x[s.dof_off + i] = (double)xs[i];
+}
+
+template <typename T, typename W, int CW>
+void solve_la_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x,
+                     const int *order, int count, int phase) {
+  if (count <= 0) return;
+  const size_t lds = ((sizeof(W) * p->max_np + 15) / 16) * 16;
+  set_lds_limit_once((const void *)k_band_solve_la<T, W, CW>, p);
+  k_band_solve_la<T, W, CW><<<count, kWideNT, lds, p->stream>>>(
+      p->subs_d, order, C, R, p->fac_entries + band_pad_back(p->max_kd), phase, b, x);
+}
+
 template <typename T, typename W, int CW, bool DB>
 void solve_wide_launch(edd_problem *p, const T *C, const T *R, const double *b, double *x,
                        const int *order, int count, int phase) {
@@ -539,29 +769,34 @@ size_t band_solve_lds_bytes(const edd_problem *p, int precision) {
 //   4, 5     wide bands (kd <= kWideRows): dedicated chain wavefront, 1024
 //            threads, 16 / 32 (FP64) or 32 / 64 (FP32) columns per load chunk
 //   6        as 4 with double-buffered load chunks
+//   7        as 6 with lookahead (k_band_solve_la)
 //   0        the default choice from the half bandwidth
 bool band_solve_variant_ok(const edd_problem *p, int v) {
   if (v >= 1 && v <= 3) return p->n_sep == 0;  // no sweep phases
-  if (v >= 4 && v <= 6) return p->max_kd <= kWideRows;
+  if (v >= 4 && v <= 7) return p->max_kd <= kWideRows;
   return v == 0;
 }
 
 // Dissected interiors: forward sweeps of all halves and whole interiors,
 // the separator right-hand sides, the separator solves, the tail updates,
 // then the backward sweeps.
-template <typename T, int CW, bool DB>
+template <typename T, int CW, bool DB, bool LA>
 static void solve_dissected(edd_problem *p, const T *C, const T *R, const T *W,
                             const double *b, double *x) {
   const int nleaf = p->n_blk - p->n_sep;
   int maxns = 0;
   for (const SepDesc &sd : p->seps) maxns = std::max(maxns, sd.ns);
-  solve_wide_launch<T, double, CW, DB>(p, C, R, b, x, p->order_leaf_d, nleaf, 1);
+  auto sweep = [&](const double *bb, const int *order, int count, int phase) {
+    if constexpr (LA) solve_la_launch<T, double, CW>(p, C, R, bb, x, order, count, phase);
+    else solve_wide_launch<T, double, CW, DB>(p, C, R, bb, x, order, count, phase);
+  };
+  sweep(b, p->order_leaf_d, nleaf, 1);
   k_sep_rhs<T><<<dim3((maxns + 63) / 64, p->n_sep), 1024, 0, p->stream>>>(p->subs_d, p->seps_d,
                                                                         W, b, x);
-  solve_wide_launch<T, double, CW, DB>(p, C, R, x, x, p->order_sep_d, p->n_sep, 0);
+  sweep(x, p->order_sep_d, p->n_sep, 0);
   k_sep_update<T><<<dim3((maxns + 7) / 8, 2 * p->n_sep), 256, 0, p->stream>>>(
       p->subs_d, p->seps_d, W, x);
-  solve_wide_launch<T, double, CW, DB>(p, C, R, x, x, p->order_leaf_d, nleaf, 2);
+  sweep(x, p->order_leaf_d, nleaf, 2);
 }
 
 void launch_band_solve(edd_problem *p, int precision, const double *b,
@@ -572,13 +807,15 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
   if (v == 0) v = p->max_kd <= 64 && p->n_sep == 0 ? 1 : (p->max_kd <= kWideRows ? 5 : 3);
   if (p->n_sep > 0) {
     if (f32) {
-      if (v == 4) solve_dissected<float, 32, false>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
-      else if (v == 6) solve_dissected<float, 32, true>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
-      else solve_dissected<float, 64, false>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+      if (v == 4) solve_dissected<float, 32, false, false>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+      else if (v == 6) solve_dissected<float, 32, true, false>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+      else if (v == 7) solve_dissected<float, 32, true, true>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
+      else solve_dissected<float, 64, false, false>(p, p->fac32_d, p->rac32_d, p->W32_d, b, x);
     } else {
-      if (v == 4) solve_dissected<double, 16, false>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
-      else if (v == 6) solve_dissected<double, 16, true>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
-      else solve_dissected<double, 32, false>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+      if (v == 4) solve_dissected<double, 16, false, false>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+      else if (v == 6) solve_dissected<double, 16, true, false>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+      else if (v == 7) solve_dissected<double, 16, true, true>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
+      else solve_dissected<double, 32, false, false>(p, p->fac64_d, p->rac64_d, p->W64_d, b, x);
     }
     return;
   }
@@ -594,6 +831,7 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
       case 3: solve_launch<float, double, 512>(p, C, R, b, x); break;
       case 4: solve_wide_launch<float, double, 32, false>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
       case 6: solve_wide_launch<float, double, 32, true>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      case 7: solve_la_launch<float, double, 32>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
       default: solve_wide_launch<float, double, 64, false>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
     }
   } else {
@@ -604,6 +842,7 @@ void launch_band_solve(edd_problem *p, int precision, const double *b,
       case 3: solve_launch<double, double, 512>(p, C, R, b, x); break;
       case 4: solve_wide_launch<double, double, 16, false>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
       case 6: solve_wide_launch<double, double, 16, true>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
+      case 7: solve_la_launch<double, double, 16>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
       default: solve_wide_launch<double, double, 32, false>(p, C, R, b, x, p->order_d, p->n_blk, 0); break;
     }
   }

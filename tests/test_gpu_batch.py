@@ -22,7 +22,7 @@ def _wide():
     return p
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5, 6, 7])
 def test_every_substitution_variant_matches_the_oracle(variant):
     require_gpu()
     from paper_1501_06211_amd import edd
@@ -42,7 +42,7 @@ def test_every_substitution_variant_matches_the_oracle(variant):
     prob.close()
 
 
-@pytest.mark.parametrize("variant", [4, 5, 6])
+@pytest.mark.parametrize("variant", [4, 5, 6, 7])
 def test_dissected_interiors_match_the_oracle(variant):
     """Every interior split into two band halves and a separator plane (one
     level of nested dissection): the same K_II^{-1} as the oracle."""
@@ -78,7 +78,7 @@ def _wider():
     return p
 
 
-@pytest.mark.parametrize("variant,dissect", [(5, 0), (6, 0), (5, 1), (6, 1)])
+@pytest.mark.parametrize("variant,dissect", [(5, 0), (6, 0), (7, 0), (5, 1), (6, 1), (7, 1)])
 def test_wide_variants_at_half_bandwidths_past_448(variant, dissect):
     require_gpu()
     from paper_1501_06211_amd import edd
@@ -134,12 +134,12 @@ def test_autotune_picks_valid_variants_and_caches():
     p = _wide()
     p64 = make_problem(p, factor_precision=edd.F64)
     v64 = p64.autotune(force=True)
-    assert 1 <= v64[0] <= 6 and v64[1] == 0  # no FP32 factors: nothing to tune
+    assert 1 <= v64[0] <= 7 and v64[1] == 0  # no FP32 factors: nothing to tune
     assert all(0 <= x <= 2 for x in v64[2:])
     p64.close()
     prob = make_problem(p)
     v = prob.autotune()  # factor precisions are part of the cache key
-    assert all(1 <= x <= 6 for x in v[:2]) and all(0 <= x <= 2 for x in v[2:])
+    assert all(1 <= x <= 7 for x in v[:2]) and all(0 <= x <= 2 for x in v[2:])
     prob2 = make_problem(p)
     assert prob2.autotune() == v  # same shape class: cached
     u, st = prob2.solve(to_cuda(p.f), tol=1e-12, maxit=3000)
