@@ -44,9 +44,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "interior_solve<double>": {
         "source": "paper_1501_06211_amd/csrc/kernels_band.hip",
-        "sha256_prefix": "15cef711506d7c9f",
+        "sha256_prefix": "ecc4db5691055191",
         "workload": "cantilever3d_simp_128x64x64",
-        "bytes": 1.4705e+10,
+        "bytes": 1.5275e+10,
         "profile": "profiles/hbm_counters_interior_solve_cantilever3d_simp_128x64x64.md",
     },
 }
