@@ -447,6 +447,10 @@ def run_topopt(args):
         prob = edd.Problem.from_workload(wk, factor_precision=edd.F64)
         f = torch.tensor(wk.f, device="cuda")
         rho = torch.full((wk.n_el,), 0.5, dtype=torch.float64, device="cuda")
+        # tile shapes and the S apply tuned once per shape class, untimed (VTS:
+        # the moduli are the densities)
+        prob.set_element_moduli(rho)
+        prob.autotune()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rho, u, st, hist = prob.topopt(f, rho, maxit=maxit, solve_opts=pc)
@@ -651,9 +655,9 @@ def main():
         prob.set_element_moduli(E)
         pv = prob.autotune()  # timed once per shape class, outside the timed region
         log(f"{prec_name}: autotuned (substitution FP64, FP32; element tiles all, interior, "
-            f"interface): {pv}")
+            f"interface): {pv}; S apply {'explicit local Schur complements' if prob.s_apply else 'through the interior factors'}")
         if info is None:
-            info, variants = prob.info, pv
+            info, variants = prob.info, list(pv) + [prob.s_apply]
         for leg in group:
             if leg.startswith("learned"):
                 if params is None:
@@ -745,7 +749,9 @@ def main():
                                  "substitution_fp32": variants[1],
                                  "element_tile_all": variants[2],
                                  "element_tile_interior": variants[3],
-                                 "element_tile_interface": variants[4]}},
+                                 "element_tile_interface": variants[4],
+                                 "s_apply": "explicit local Schur complements" if variants[5]
+                                            else "interior factors"}},
         "config": {"workload": w.name, "ndof": int(w.ndof), "subdomains": int(w.n_sub),
                    "path": head, "precond": args.precond, "tol": args.tol,
                    "step": "set_element_moduli + solve from zero",

@@ -340,7 +340,10 @@ int edd_solve_batch(edd_problem *const *ps, int n, const double *const *f_dev,
  *  - the element kernel: node tiles of 16x16 / 32x8 / 64x4 (2D) or 8x8x4 /
  *    16x4x4 / 16x8x2 (3D) nodes (every shape gives bitwise the same result),
  *    chosen separately for the full product, the product on interior nodes
- *    and the product on interface nodes (the two halves of an S apply).
+ *    and the product on interface nodes (the two halves of an S apply);
+ *  - the S apply (edd_set_s_apply): explicit local Schur complements where
+ *    the problem allows them, if their FP64 apply is faster (the choice is
+ *    applied to the handle; edd_get_s_apply reports it).
  * The fastest of each is kept.  Choices are cached per (device
  * architecture, kernel family, shape class: dimension, band extents and
  * factor precisions for the substitution, the node grid for the element
@@ -357,6 +360,27 @@ int edd_autotune(edd_problem *p, int force, int *variants);
 int edd_autotune_cache(const char *path);
 /* Choose the substitution variants by hand (0 = default by bandwidth). */
 int edd_set_solve_variants(edd_problem *p, const int *variants);
+/* How S v is applied (the Steklov-Poincare splitting S = sum_i R_i^T S_i R_i
+ * over the subdomains, Section 1; the subdomain problems of eq.
+ * (3MatSplit2)):
+ *   0  through the interior factors: S v = (K[-K_II^{-1}(K[0;v])_I ; v])_G
+ *      (the default);
+ *   1  explicit local Schur complements S_i = K^i_GG - K^i_GI (K^i_II)^{-1}
+ *      K^i_IG on the interface dofs of each subdomain's closure (its own
+ *      elements), formed on the device after every edd_set_element_moduli
+ *      from the FP64 interior factors (a forward substitution with all
+ *      right-hand sides, then K^i_GG - Y^T Y), stored dense (sum_i m_i^2
+ *      doubles) and applied as one dense matrix-vector product per
+ *      subdomain plus a fixed-order sum over the subdomains of each
+ *      interface dof.
+ * Mode 1 serves FP64 applies (FP32 applies of the mixed modes keep mode 0)
+ * and needs undissected interiors, FP64 factors and m_i <= 1024 with the
+ * formation's LDS ring fitting one workgroup: EDD_EINVAL otherwise (2D
+ * decompositions qualify; 3D ones only with small subdomains).  The
+ * element-kernel timings (edd_get_kernel_times) do not include it.
+ * Synchronises when it forms S_i. */
+int edd_set_s_apply(edd_problem *p, int mode);
+int edd_get_s_apply(edd_problem *p, int *mode);
 /* Choose the element kernel's node-tile shape by hand (0..2, as above) for
  * all three kinds of target. */
 int edd_set_apply_variant(edd_problem *p, int variant);

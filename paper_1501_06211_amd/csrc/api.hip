@@ -127,6 +127,10 @@ KTimer::~KTimer() {
 
 // y = S v on interface vectors; t is an interior-length work vector
 void apply_S_with(edd_problem *p, const double *v, double *y, int prec, double *t) {
+  if (p->s_apply_mode == 1 && p->sc_ready && prec != EDD_F32) {
+    schur_apply(p, v, y);  // explicit local Schur complements (FP64)
+    return;
+  }
   launch_apply_mapped(p, p->inode_d, p->n_inodes, nullptr, 0.0, v, 1.0, nullptr,
                       1.0, t);
   launch_band_solve(p, prec, t, t);
@@ -903,6 +907,7 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
 int edd_set_element_moduli(edd_problem *p, const void *E_dev, int dtype) {
   if (!p || !E_dev || (dtype != EDD_F64 && dtype != EDD_F32)) return EDD_EINVAL;
   p->have_moduli = false;
+  p->sc_ready = false;
   launch_convert_moduli(p, E_dev, dtype);
   launch_check_moduli(p, p->E_d, p->partials_d);
   launch_reduce(p, 256, 1, 1, S_BAD);
@@ -925,6 +930,11 @@ int edd_set_element_moduli(edd_problem *p, const void *E_dev, int dtype) {
   if (rc) return rc;
   p->have_moduli = true;
   p->sk_state = -1;  // weighted interface operators must be rebuilt
+  if (p->s_apply_mode == 1) {
+    rc = schur_form(p);
+    if (!rc) rc = sync_check(p);
+    if (rc) return rc;
+  }
   return EDD_OK;
 }
 
@@ -1038,8 +1048,9 @@ int edd_get_interior_nodes(edd_problem *p, int32_t *nodes_host) {
 // Autotuner cache: in memory for the process, and in a text file when one is
 // set (edd_autotune_cache): one line per tuned (kernel family, shape class),
 //   <family> <key> <value> [<value>]
-// with family band_solve (FP64 and FP32 substitution variants) or apply_K
-// (node-tile shape), key = architecture|shape class.
+// with family band_solve (FP64 and FP32 substitution variants), apply_K
+// (node-tile shape) or s_apply (0 through the factors, 1 explicit local
+// Schur complements), key = architecture|shape class.
 namespace {
 std::mutex g_tune_mu;
 std::map<std::string, std::vector<int>> g_tune;
@@ -1197,6 +1208,60 @@ int edd_autotune(edd_problem *p, int force, int *variants) {
     if (need_band) g_tune[kb] = {p->solve_variant[0], p->solve_variant[1]};
     if (need_apply) g_tune[ka] = {p->apply_variant[0], p->apply_variant[1], p->apply_variant[2]};
     tune_save_locked();
+  }
+  // the S apply: through the interior factors or by explicit local Schur
+  // complements (where the problem allows them); cached per shape class
+  {
+    const std::string ks = "s_apply " + arch + "|" + std::to_string(p->g.dim) + "|" +
+                           std::to_string(p->g.nn[0]) + "x" + std::to_string(p->g.nn[1]) + "x" +
+                           std::to_string(p->g.nn[2]) + "|" + std::to_string(p->n_sub) + "|" +
+                           std::to_string(p->factor_precision);
+    int cached = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(ks);
+      if (!force && it != g_tune.end() && it->second.size() == 1) cached = it->second[0];
+    }
+    if (cached >= 0) {
+      rc = edd_set_s_apply(p, cached);
+      if (rc == EDD_EINVAL && cached == 1) rc = edd_set_s_apply(p, 0);
+      if (rc) return rc;
+    } else {
+      int best = 0;
+      if (schur_setup(p) == EDD_OK) {
+        hipEvent_t e0, e1;
+        rc = check_hip(p, hipEventCreate(&e0));
+        if (rc) return rc;
+        rc = check_hip(p, hipEventCreate(&e1));
+        if (rc) return rc;
+        const int64_t nG = p->n_gamma * p->g.dim;
+        double *v = p->w_G[6], *y = p->w_G[7];
+        launch_fill(p, nG, 1.0, v);
+        const bool kt = p->kt_enabled;
+        p->kt_enabled = false;
+        float ms[2] = {0.0f, 0.0f};
+        for (int mode = 0; mode < 2 && rc == 0; ++mode) {
+          rc = edd_set_s_apply(p, mode);
+          if (rc) break;
+          apply_S(p, v, y, EDD_F64);  // warm-up
+          hipEventRecord(e0, p->stream);
+          for (int r = 0; r < 5; ++r) apply_S(p, v, y, EDD_F64);
+          hipEventRecord(e1, p->stream);
+          rc = check_hip(p, hipEventSynchronize(e1));
+          if (!rc) rc = check_hip(p, hipEventElapsedTime(&ms[mode], e0, e1));
+        }
+        p->kt_enabled = kt;
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (rc) return rc;
+        best = ms[1] < ms[0] ? 1 : 0;
+      }
+      rc = edd_set_s_apply(p, best);
+      if (rc) return rc;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[ks] = {best};
+      tune_save_locked();
+    }
   }
   if (variants) {
     variants[0] = p->solve_variant[0];

@@ -69,6 +69,22 @@ struct SubDesc {
   int64_t fac_off;  // offset in band storage (entries)
 };
 
+// One subdomain's explicit local Schur complement S_i = K^i_GG -
+// K^i_GI (K^i_II)^{-1} K^i_IG (its own elements only) on the m = dim*mg
+// interface dofs of its closure, local order: the closure's interface nodes
+// by node id, components fastest.  S_i is dense row-major at s_off; Y (the
+// forward-substituted couplings, n x m row-major) at y_off; the apply's
+// local output at l_off; the interface positions of the local nodes at
+// g_off; the closure box (node coordinates c_lo, extents c_ext) maps to local
+// interface node indices (or -1) at t_off; elements e_lo .. e_hi (inclusive).
+struct SchurDesc {
+  int blk;          // band block of the subdomain's interior
+  int m, mg;
+  int c_lo[3], c_ext[3];
+  int e_lo[3], e_hi[3];
+  int64_t s_off, y_off, l_off, g_off, t_off;
+};
+
 // what a captured preconditioner graph was recorded for
 struct PcGraphKey {
   const double *r = nullptr;
@@ -146,6 +162,15 @@ struct edd_problem {
   int *order_d = nullptr;
   int *order_leaf_d = nullptr, *order_sep_d = nullptr;
   edd::SepDesc *seps_d = nullptr;
+  // explicit local Schur complements (S apply by dense GEMVs), see SchurDesc
+  int s_apply_mode = 0;       // 0: through the interior factors; 1: explicit S_i
+  bool sc_ready = false;      // S_i formed for the current moduli
+  int sc_max_m = 0, sc_max_mg = 0;
+  std::vector<edd::SchurDesc> sc_desc;
+  edd::SchurDesc *sc_desc_d = nullptr;
+  int *sc_gl_d = nullptr, *sc_tab_d = nullptr, *sc_optr_d = nullptr, *sc_oent_d = nullptr;
+  double *sc_S_d = nullptr, *sc_Y_d = nullptr, *sc_yl_d = nullptr;
+  int64_t sc_S_len = 0, sc_Y_len = 0;
   double *W64_d = nullptr;  // separator couplings (see SepDesc)
   float *W32_d = nullptr;
   int *info_d = nullptr;     // per-subdomain factorisation status
@@ -289,6 +314,13 @@ void launch_band_layouts(edd_problem *p);
 void launch_band_solve(edd_problem *p, int precision, const double *b,
                        double *x);
 bool band_solve_variant_ok(const edd_problem *p, int v);
+
+// schur.hip / kernels_fe.hip: explicit local Schur complements
+int schur_setup(edd_problem *p);   // tables and storage; EDD_EINVAL if not eligible
+int schur_form(edd_problem *p);    // S_i from the current moduli and FP64 factors
+void schur_apply(edd_problem *p, const double *v, double *y);
+void launch_schur_couplings(edd_problem *p);  // Y_i = K^i_IG (rows of the band order)
+void launch_schur_kgg(edd_problem *p);        // S_i += K^i_GG
 constexpr int kBandSolveVariants = 7;
 constexpr int kApplyVariants = 3;  // node-tile shapes of the element kernel
 

@@ -436,6 +436,91 @@ inline unsigned grid_for(int64_t n) {
   return (unsigned)((n + kBlock - 1) / kBlock);
 }
 
+// ---- explicit local Schur complements: the element parts -----------------
+// Local interface index of the node at global coordinates (x, y, z) in
+// subdomain sd's closure table, or -1.
+__device__ inline int schur_local(const SchurDesc &sd, const int *__restrict__ tab, int x, int y,
+                                  int z) {
+  const int tx = x - sd.c_lo[0], ty = y - sd.c_lo[1], tz = z - sd.c_lo[2];
+  if (tx < 0 || ty < 0 || tz < 0 || tx >= sd.c_ext[0] || ty >= sd.c_ext[1] || tz >= sd.c_ext[2])
+    return -1;
+  return tab[sd.t_off + tx + (int64_t)sd.c_ext[0] * (ty + (int64_t)sd.c_ext[1] * tz)];
+}
+
+// Y_i[r][j] = K^i(interior dof r, local interface dof j), r in the band
+// order of the subdomain's interior (every element around an interior node
+// belongs to the subdomain).  One workgroup per subdomain, a thread per row.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_schur_couplings(
+    Geom g, const double *__restrict__ K0, const double *__restrict__ E,
+    const SubDesc *__restrict__ subs, const SchurDesc *__restrict__ sds,
+    const int *__restrict__ tab, double *__restrict__ Y) {
+  constexpr int NC = (D == 3) ? 8 : 4, ND = D * NC;
+  const SchurDesc sd = sds[blockIdx.x];
+  const SubDesc s = subs[sd.blk];
+  const int m = sd.m;
+  double *Yi = Y + sd.y_off;
+  for (int r = threadIdx.x; r < s.n; r += blockDim.x) {
+    double *row = Yi + (int64_t)r * m;
+    for (int j = 0; j < m; ++j) row[j] = 0.0;
+    int x[3], c;
+    block_coords(s, D, r, x, c);
+    for (int dz = (D == 3 ? -1 : 0); dz <= 0; ++dz)
+      for (int dy = -1; dy <= 0; ++dy)
+        for (int dx = -1; dx <= 0; ++dx) {
+          const int ex = x[0] + dx, ey = x[1] + dy, ez = x[2] + dz;
+          if (ex < 0 || ey < 0 || ez < 0 || ex >= g.nel[0] || ey >= g.nel[1] ||
+              (D == 3 && ez >= g.nel[2]))
+            continue;
+          const double Ee = E[ex + (int64_t)g.nel[0] * (ey + (int64_t)g.nel[1] * ez)];
+          const int ar = corner_of(x[0] - ex, x[1] - ey, D == 3 ? x[2] - ez : 0);
+          for (int k = 0; k < NC; ++k) {
+            const int jn = schur_local(sd, tab, ex + corner_x(k), ey + corner_y(k),
+                                       ez + (D == 3 ? corner_z(k) : 0));
+            if (jn < 0) continue;
+            for (int c2 = 0; c2 < D; ++c2)
+              row[jn * D + c2] = fma(Ee, K0[(k * D + c2) * ND + ar * D + c], row[jn * D + c2]);
+          }
+        }
+  }
+}
+
+// S_i[a][b] += K^i_GG[a][b] over the subdomain's own elements (e_lo..e_hi).
+// One workgroup per subdomain, a thread per row a.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_schur_kgg(
+    Geom g, const double *__restrict__ K0, const double *__restrict__ E,
+    const SchurDesc *__restrict__ sds, const int *__restrict__ gl,
+    const int *__restrict__ gnode, const int *__restrict__ tab, double *__restrict__ S) {
+  constexpr int NC = (D == 3) ? 8 : 4, ND = D * NC;
+  const SchurDesc sd = sds[blockIdx.x];
+  const int m = sd.m;
+  double *Si = S + sd.s_off;
+  for (int a = threadIdx.x; a < m; a += blockDim.x) {
+    const int an = a / D, c = a - an * D;
+    const int node = gnode[gl[sd.g_off + an]];
+    const int x[3] = {node % g.nn[0], (node / g.nn[0]) % g.nn[1], node / (g.nn[0] * g.nn[1])};
+    double *row = Si + (int64_t)a * m;
+    for (int dz = (D == 3 ? -1 : 0); dz <= 0; ++dz)
+      for (int dy = -1; dy <= 0; ++dy)
+        for (int dx = -1; dx <= 0; ++dx) {
+          const int ex = x[0] + dx, ey = x[1] + dy, ez = x[2] + dz;
+          if (ex < sd.e_lo[0] || ey < sd.e_lo[1] || ez < sd.e_lo[2] || ex > sd.e_hi[0] ||
+              ey > sd.e_hi[1] || ez > sd.e_hi[2])
+            continue;
+          const double Ee = E[ex + (int64_t)g.nel[0] * (ey + (int64_t)g.nel[1] * ez)];
+          const int aa = corner_of(x[0] - ex, x[1] - ey, D == 3 ? x[2] - ez : 0);
+          for (int k = 0; k < NC; ++k) {
+            const int jn = schur_local(sd, tab, ex + corner_x(k), ey + corner_y(k),
+                                       ez + (D == 3 ? corner_z(k) : 0));
+            if (jn < 0) continue;
+            for (int c2 = 0; c2 < D; ++c2)
+              row[jn * D + c2] = fma(Ee, K0[(k * D + c2) * ND + aa * D + c], row[jn * D + c2]);
+          }
+        }
+  }
+}
+
 }  // namespace
 
 template <int D, int MODE, int TGT, int V>
@@ -502,6 +587,26 @@ void launch_assemble_band(edd_problem *p) {
   if (p->n_sep > 0 && p->g.dim == 3)
     k_assemble_coupling<3><<<dim3(64, 2 * p->n_sep), kBlock, 0, p->stream>>>(
         p->g, p->K0_d, p->E_d, p->subs_d, p->seps_d, p->W64_d);
+}
+
+void launch_schur_couplings(edd_problem *p) {
+  const int n = (int)p->sc_desc.size();
+  if (p->g.dim == 2)
+    k_schur_couplings<2><<<n, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d, p->subs_d,
+                                                       p->sc_desc_d, p->sc_tab_d, p->sc_Y_d);
+  else
+    k_schur_couplings<3><<<n, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d, p->subs_d,
+                                                       p->sc_desc_d, p->sc_tab_d, p->sc_Y_d);
+}
+
+void launch_schur_kgg(edd_problem *p) {
+  const int n = (int)p->sc_desc.size();
+  if (p->g.dim == 2)
+    k_schur_kgg<2><<<n, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d, p->sc_desc_d,
+                                                 p->sc_gl_d, p->gnode_d, p->sc_tab_d, p->sc_S_d);
+  else
+    k_schur_kgg<3><<<n, kBlock, 0, p->stream>>>(p->g, p->K0_d, p->E_d, p->sc_desc_d,
+                                                 p->sc_gl_d, p->gnode_d, p->sc_tab_d, p->sc_S_d);
 }
 
 void launch_gather(edd_problem *p, const int *nodes, int64_t n,

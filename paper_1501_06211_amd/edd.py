@@ -39,7 +39,7 @@ EXPORTS = [
     "edd_set_solve_variants", "edd_apply_S_noalloc", "edd_cnn_training_pair",
     "edd_element_energies", "edd_oc_update", "edd_default_topopt_opts", "edd_topopt_run",
     "edd_solve_gmres", "edd_autotune_cache", "edd_set_apply_variant",
-    "edd_cnn_matrix_cores",
+    "edd_cnn_matrix_cores", "edd_set_s_apply", "edd_get_s_apply",
 ]
 NOALLOC_MAX_INTERIOR_DOFS = 1 << 21
 KT_NAMES = ["band_solve", "band_cholesky", "apply_K", "apply_mapped", "assemble",
@@ -219,6 +219,8 @@ def lib():
     L.edd_autotune_cache.argtypes = [ctypes.c_char_p]
     L.edd_set_apply_variant.argtypes = [vp, i32]
     L.edd_set_solve_variants.argtypes = [vp, ctypes.POINTER(i32)]
+    L.edd_set_s_apply.argtypes = [vp, i32]
+    L.edd_get_s_apply.argtypes = [vp, ctypes.POINTER(i32)]
     L.edd_cnn_setup.argtypes = [vp, i32]
     L.edd_cnn_matrix_cores.argtypes = [vp, i32]
     L.edd_cnn_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
@@ -435,6 +437,17 @@ class Problem:
     def set_solve_variants(self, f64, f32):
         v = (ctypes.c_int * 2)(int(f64), int(f32))
         self._check(lib().edd_set_solve_variants(self.h, v), "edd_set_solve_variants")
+
+    def set_s_apply(self, mode):
+        """0: S v through the interior factors; 1: explicit local Schur
+        complements (see edd_set_s_apply)."""
+        self._check(lib().edd_set_s_apply(self.h, int(mode)), "edd_set_s_apply")
+
+    @property
+    def s_apply(self):
+        m = ctypes.c_int()
+        self._check(lib().edd_get_s_apply(self.h, ctypes.byref(m)), "edd_get_s_apply")
+        return int(m.value)
 
     # ---- correction network -------------------------------------------------
     def _nparams(self):

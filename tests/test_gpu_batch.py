@@ -216,7 +216,7 @@ def test_autotune_cache_file(tmp_path):
         v = prob.autotune(force=True)
         lines = open(path).read().splitlines()
         fams = sorted(l.split()[0] for l in lines)
-        assert fams == ["apply_K", "band_solve"]
+        assert fams == ["apply_K", "band_solve", "s_apply"]
         # edit the stored tile shapes; a reload must return the file's values
         other = [(x + 1) % 3 for x in v[2:]]
         edited = [(" ".join(l.split()[:2] + [str(x) for x in other])
