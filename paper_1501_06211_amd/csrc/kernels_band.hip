@@ -24,15 +24,23 @@
 
 namespace edd {
 
-// Raise a kernel's dynamic LDS limit to the device's, once per (kernel,
-// device); thread-safe.
+// Raise a kernel's dynamic LDS limit to what the device leaves beside the
+// kernel's static LDS, once per (kernel, device); thread-safe.  A refused
+// raise is not an error here (its error state is consumed): a launch that
+// then asks for more than the default limit fails on its own.
 void set_lds_limit_once(const void *kernel, const edd_problem *p) {
   static std::mutex mu;
   static std::vector<std::pair<const void *, int>> done;
   std::lock_guard<std::mutex> lk(mu);
   for (const auto &d : done)
     if (d.first == kernel && d.second == p->device) return;
-  hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds_limit);
+  hipFuncAttributes fa{};
+  size_t stat = 0;
+  if (hipFuncGetAttributes(&fa, kernel) == hipSuccess) stat = fa.sharedSizeBytes;
+  else (void)hipGetLastError();
+  const int dyn = (int)(p->lds_limit > stat ? p->lds_limit - stat : 0);
+  if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess)
+    (void)hipGetLastError();
   done.emplace_back(kernel, p->device);
 }
 

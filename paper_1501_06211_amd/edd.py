@@ -345,6 +345,8 @@ class Problem:
 
     def _check(self, rc, what):
         if rc not in (OK, NOT_CONVERGED):
+            if rc == EHIP:
+                what = f"{what} (hipError_t {lib().edd_last_hip_error(self.h)})"
             raise EddError(rc, what)
         return rc
 
