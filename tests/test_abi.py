@@ -48,3 +48,36 @@ def test_binding_struct_layout_and_defaults():
     h = ctypes.c_void_p()
     assert L.edd_setup_mesh(ctypes.byref(d), None, None, ctypes.byref(h)) == edd.EINVAL
     assert L.edd_destroy(None) == edd.OK
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror of a header struct has the header's field offsets
+    and size, as a C compiler lays them out."""
+    import shutil
+    import subprocess
+    from paper_1501_06211_amd import edd
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [(edd.Allocator, "edd_allocator"), (edd.MeshDesc, "edd_mesh_desc"),
+             (edd.SolveOpts, "edd_solve_opts"), (edd.SolveStats, "edd_solve_stats"),
+             (edd.Info, "edd_info"), (edd.OcParams, "edd_oc_params"),
+             (edd.OcResult, "edd_oc_result"), (edd.TopoptOpts, "edd_topopt_opts"),
+             (edd.TopoptStats, "edd_topopt_stats"), (edd.KernelTimes, "edd_kernel_times")]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "edd.h"', "int main(void) {"]
+    for cls, cname in pairs:
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:  # a trailing _ avoids a Python keyword (lambda_)
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0].rstrip("_")}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln}
+    for cls, cname in pairs:
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
