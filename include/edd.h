@@ -176,6 +176,14 @@ typedef struct edd_solve_opts {
                       /* a step without a usable direction is dropped (flag   */
                       /* EDD_FLAG_LEARNED_REJECTED); needs edd_cnn_setup;     */
                       /* 0: off                                               */
+  int mass_matrix;    /* skeleton mass matrix M of the interface norm        */
+                      /* (Section 3): 0 lumped (row sums, diagonal: M^{-1}  */
+                      /* and the M inner products are exact scalings), 1    */
+                      /* the consistent FE mass matrix (its products are    */
+                      /* sparse products in the pattern of L; M^{-1} by     */
+                      /* Chebyshev iteration on the Jacobi-scaled M, whose  */
+                      /* spectrum the element matrices bound: [1/2, 3/2]    */
+                      /* in 2D, [1/4, 9/4] in 3D, to 1e-12)                  */
 } edd_solve_opts;
 
 typedef struct edd_solve_stats {
@@ -288,6 +296,9 @@ int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
  *   which 1: y = M x     (lumped skeleton mass)
  *   which 2: y = B^{-1} x (L restricted to the faces, cross points removed)
  *   which 3: y ~ L^{-1} x by PCG with B (relative tolerance tol, maxit)
+ *   which 4: y = M x     (consistent skeleton mass)
+ *   which 5: y ~ M^{-1} x (consistent mass, the Chebyshev iteration of the
+ *            mass_matrix = 1 preconditioner)
  * weighting as edd_solve_opts.interface_weighting (1 needs moduli).
  * Synchronises for which 3. */
 int edd_apply_skeleton_op(edd_problem *p, int which, int weighting,

@@ -228,7 +228,7 @@ static int fcg_graph_iterations(edd_problem *p, double *x, int prec, double tol_
   oc.use_graphs = 0;  // the preconditioner's kernels go into this graph directly
   const double th = o->theta;
   int64_t key[12] = {N, cap, prec, (int64_t)(uintptr_t)x, o->precond, o->lanczos_kmax,
-                     o->inner_maxit, o->interface_weighting, o->pc_form, 0, 0, nG};
+                     o->inner_maxit, o->interface_weighting, o->pc_form, 0, o->mass_matrix, nG};
   std::memcpy(&key[9], &th, sizeof th);
   if (!p->fcg_graph || std::memcmp(key, p->fcg_graph_key, sizeof key) != 0) {
     if (p->fcg_graph) {
@@ -729,6 +729,7 @@ void edd_default_opts(edd_solve_opts *o) {
   o->use_graphs = 0;
   o->pc_form = EDD_PCF_HTILDE_INV;
   o->learned_correction = 0;
+  o->mass_matrix = 0;
 }
 
 const char *edd_strerror(int code) {
@@ -973,7 +974,8 @@ int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
   }
   if (o->interface_weighting && !p->have_moduli) return EDD_ESTATE;
   if (o->lanczos_kmax < 1 || o->lanczos_kmax > 64 || o->inner_maxit < 1 ||
-      o->pc_form < EDD_PCF_HTILDE_INV || o->pc_form > EDD_PCF_H_FWD)
+      o->pc_form < EDD_PCF_HTILDE_INV || o->pc_form > EDD_PCF_H_FWD ||
+      (o->mass_matrix != 0 && o->mass_matrix != 1))
     return EDD_EINVAL;
   edd_solve_stats st{};
   int rc = precond_apply(p, r_dev, z_dev, o, &st, o->precision == EDD_MODE_MIXED);
@@ -983,7 +985,7 @@ int edd_apply_precond(edd_problem *p, const double *r_dev, double *z_dev,
 
 int edd_apply_skeleton_op(edd_problem *p, int which, int weighting,
                           const double *x_dev, double *y_dev, double tol, int maxit) {
-  if (!p || !x_dev || !y_dev || which < 0 || which > 3) return EDD_EINVAL;
+  if (!p || !x_dev || !y_dev || which < 0 || which > 5) return EDD_EINVAL;
   if (weighting && !p->have_moduli) return EDD_ESTATE;
   if (which == 3 && (maxit < 1 || !(tol >= 0.0))) return EDD_EINVAL;
   int rc = skeleton_op(p, which, weighting, x_dev, y_dev, tol, maxit);
@@ -1420,7 +1422,8 @@ int edd_solve_interface(edd_problem *p, const double *f_dev, double *u_dev,
   if (o.precond != EDD_PC_IDENTITY && o.precond != EDD_PC_HTHETA) return EDD_EINVAL;
   if (o.precond == EDD_PC_HTHETA &&
       (o.lanczos_kmax < 1 || o.lanczos_kmax > 64 || o.inner_maxit < 1 || o.theta > 1.0 ||
-       o.pc_form < EDD_PCF_HTILDE_INV || o.pc_form > EDD_PCF_H_FWD))
+       o.pc_form < EDD_PCF_HTILDE_INV || o.pc_form > EDD_PCF_H_FWD ||
+       (o.mass_matrix != 0 && o.mass_matrix != 1)))
     return EDD_EINVAL;
   if (o.precision != EDD_MODE_F64 && o.precision != EDD_MODE_MIXED &&
       o.precision != EDD_MODE_RELAXED)

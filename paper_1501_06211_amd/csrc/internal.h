@@ -91,10 +91,10 @@ struct PcGraphKey {
   double *z = nullptr;
   int k = 0, inner = 0, weighting = 0;
   double theta = 0.0;
-  int form = 0;
+  int form = 0, mass = 0;
   bool operator==(const PcGraphKey &o) const {
     return r == o.r && z == o.z && k == o.k && inner == o.inner && weighting == o.weighting &&
-           theta == o.theta && form == o.form;
+           theta == o.theta && form == o.form && mass == o.mass;
   }
 };
 
@@ -198,6 +198,10 @@ struct edd_problem {
   int *skC_elem_d = nullptr, *skC_ab_d = nullptr;
   int *skN_ptr_d = nullptr, *skN_elem_d = nullptr;  // skeleton elements per node
   double *skM_d = nullptr;      // lumped mass (diagonal)
+  double *skMc_val_d = nullptr; // consistent mass, values in the pattern of L
+  double *skMcdiag_d = nullptr; // its diagonal
+  double sk_Me[16] = {};        // skeleton element mass matrix (unit element)
+  double sk_cheb_lo = 0.0, sk_cheb_hi = 0.0;  // bounds of diag(M)^{-1} M
   double *skLdiag_d = nullptr;  // diagonal of L (current weighting)
   double *skL0diag_d = nullptr; // diagonal of the unweighted L
   double *skS_d = nullptr;      // face-block scaling sqrt(Ldiag / L0diag)
@@ -215,7 +219,8 @@ struct edd_problem {
   // Lanczos / inner PCG work space
   int pc_kcap = 0;
   double *pc_Q_d = nullptr;     // basis vectors
-  double *pc_v_d[8] = {};       // work vectors (gamma-sized)
+  double *pc_v_d[9] = {};       // work vectors (gamma-sized)
+  double *pc_MQ_d = nullptr;    // M times the basis vectors (consistent M)
   double *pc_h = nullptr;       // pinned host buffer for coefficients
 
   // captured interface iterations (use_graphs >= 2)

@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_sk_weights(
   w[e] = weighted ? 0.5 * (E[adj[2 * e]] + E[adj[2 * e + 1]]) : 1.0;
 }
 
-struct ElemMat {
-  double Le[16];
+struct ElemMat {  // an element matrix of the skeleton (L or M), row-major
+  double v[16];
 };
 
 __global__ __launch_bounds__(kBlock) void k_sk_assemble(
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_sk_assemble(
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= nnz) return;
   double s = 0.0;
-  for (int t = cptr[k]; t < cptr[k + 1]; ++t) s = fma(w[celem[t]], em.Le[cab[t]], s);
+  for (int t = cptr[k]; t < cptr[k + 1]; ++t) s = fma(w[celem[t]], em.v[cab[t]], s);
   val[k] = s;
 }
 
@@ -127,6 +127,74 @@ __global__ __launch_bounds__(kBlock) void k_sk_diag(
     if (col[k] == i) d = val[k];
   Ld[i] = d;
   S[i] = sqrt(d / l0[i]);
+}
+
+// diag[i] = the (i, i) entry of a CSR matrix
+__global__ __launch_bounds__(kBlock) void k_csr_diag(int64_t n, const int *__restrict__ rowptr,
+                                                     const int *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     double *__restrict__ diag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+    if (col[k] == i) d = val[k];
+  diag[i] = d;
+}
+
+// Chebyshev iteration for the consistent skeleton mass, M x = b, scaled by
+// diag(M) (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1,
+// with the Jacobi preconditioner), the spectrum of diag(M)^{-1} M inside
+// [th - de, th + de]:
+//   x_0 = 0, r_0 = b, d_0 = diag(M)^{-1} r_0 / th, rho_0 = de / th;
+//   x_{k+1} = x_k + d_k, r_{k+1} = r_k - M d_k,
+//   rho_{k+1} = 1 / (2 th / de - rho_k),
+//   d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / de) diag(M)^{-1} r_{k+1}.
+// Each component of the D interleaved ones is an independent system.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cheb_init(int64_t nG, const double *__restrict__ diag,
+                                                      double inv_th, const double *__restrict__ b,
+                                                      double *__restrict__ x,
+                                                      double *__restrict__ r,
+                                                      double *__restrict__ d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nG) return;
+  const double s = inv_th / diag[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double v = b[i * D + c];
+    x[i * D + c] = 0.0;
+    r[i * D + c] = v;
+    d[i * D + c] = s * v;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_cheb_step(
+    int64_t nG, const int *__restrict__ rowptr, const int *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ diag,
+    const double *__restrict__ d_in, double *__restrict__ d_out, double *__restrict__ x,
+    double *__restrict__ r, double c1, double c2) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nG) return;
+  double acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = 0.0;
+  for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+    const double v = val[k];
+    const int64_t j = col[k];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = fma(v, d_in[j * D + c], acc[c]);
+  }
+  const double s = c2 / diag[i];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double dv = d_in[i * D + c];
+    x[i * D + c] += dv;
+    const double rv = r[i * D + c] - acc[c];
+    r[i * D + c] = rv;
+    d_out[i * D + c] = fma(c1, dv, s * rv);
+  }
 }
 
 // y = L x for D interleaved components
@@ -880,16 +948,33 @@ static void skeleton_element_matrices(int dim, double *Le, double *Me) {
     }
 }
 
+namespace {
+void jacobi_eig(int k, std::vector<double> &A, std::vector<double> &U, std::vector<double> &lam);
+}  // namespace
+
 int precond_setup(edd_problem *p) {
   const int D = p->g.dim;
   const int64_t nG = p->n_gamma;
   if (nG == 0) return EDD_OK;
   const int npe = D == 2 ? 2 : 4;
   p->sk_npe = npe;
-  double Me[16];
-  skeleton_element_matrices(D, p->sk_Le, Me);
+  skeleton_element_matrices(D, p->sk_Le, p->sk_Me);
+  const double *Me = p->sk_Me;
   p->sk_rowsum = 0.0;
   for (int b = 0; b < npe; ++b) p->sk_rowsum += Me[b];  // equal for every row
+  {
+    // spectrum of diag(M)^{-1} M for the consistent mass: every element's
+    // generalised eigenvalues of (Me, diag(Me)) bound it, for any positive
+    // element weights and with clamped rows removed (Rayleigh quotients of
+    // sums of element forms); widened by a hair against rounding
+    std::vector<double> A((size_t)npe * npe), U, lam;
+    for (int a = 0; a < npe; ++a)
+      for (int b = 0; b < npe; ++b)
+        A[a * npe + b] = Me[a * npe + b] / std::sqrt(Me[a * npe + a] * Me[b * npe + b]);
+    jacobi_eig(npe, A, U, lam);
+    p->sk_cheb_lo = *std::min_element(lam.begin(), lam.end()) * (1.0 - 1e-9);
+    p->sk_cheb_hi = *std::max_element(lam.begin(), lam.end()) * (1.0 + 1e-9);
+  }
   const auto &nn = p->g.nn;
   auto nid = [&](int x, int y, int z) -> int64_t {
     return x + (int64_t)nn[0] * (y + (int64_t)nn[1] * z);
@@ -1123,6 +1208,8 @@ int precond_setup(edd_problem *p) {
   PC_ALLOC(p->skN_ptr_d, int, nG + 1);
   PC_ALLOC(p->skN_elem_d, int, nelem.size());
   PC_ALLOC(p->skM_d, double, nG);
+  PC_ALLOC(p->skMc_val_d, double, nnz);
+  PC_ALLOC(p->skMcdiag_d, double, nG);
   PC_ALLOC(p->skLdiag_d, double, nG);
   PC_ALLOC(p->skL0diag_d, double, nG);
   PC_ALLOC(p->skS_d, double, nG);
@@ -1150,7 +1237,7 @@ int precond_setup(edd_problem *p) {
             up(p->rest_d, rest.data(), sizeof(int) * rest.size()) &&
             up(p->face_inv_d, inv_all.data(), sizeof(double) * inv_all.size());
   if (!ok || hipStreamSynchronize(p->stream) != hipSuccess) return EDD_EHIP;
-  for (int i = 0; i < 8; ++i) PC_ALLOC(p->pc_v_d[i], double, nG * D);
+  for (int i = 0; i < 9; ++i) PC_ALLOC(p->pc_v_d[i], double, nG * D);
   if (hipHostMalloc((void **)&p->pc_h, sizeof(double) * 65 * 3) != hipSuccess)
     return EDD_ENOMEM;
 #undef PC_ALLOC
@@ -1165,12 +1252,19 @@ static int precond_operators(edd_problem *p, int weighting) {
   k_sk_weights<<<grid_for(p->sk_n), kBlock, 0, p->stream>>>(
       p->sk_n, p->sk_adj_d, p->E_d, weighting, p->sk_w_d);
   ElemMat em;
-  std::memcpy(em.Le, p->sk_Le, sizeof(em.Le));
+  std::memcpy(em.v, p->sk_Le, sizeof(em.v));
   k_sk_assemble<<<(unsigned)((p->sk_nnz + kBlock - 1) / kBlock), kBlock, 0, p->stream>>>(
       p->sk_nnz, p->skC_ptr_d, p->skC_elem_d, p->skC_ab_d, p->sk_w_d, em, p->skL_val_d);
   k_sk_diag<<<(unsigned)((nG + kBlock - 1) / kBlock), kBlock, 0, p->stream>>>(
       nG, p->skN_ptr_d, p->skN_elem_d, p->sk_w_d, p->sk_rowsum, p->skL_rowptr_d,
       p->skL_col_d, p->skL_val_d, p->skL0diag_d, p->skM_d, p->skLdiag_d, p->skS_d);
+  // the consistent mass in the same pattern, from the same contributions
+  ElemMat mm;
+  std::memcpy(mm.v, p->sk_Me, sizeof(mm.v));
+  k_sk_assemble<<<(unsigned)((p->sk_nnz + kBlock - 1) / kBlock), kBlock, 0, p->stream>>>(
+      p->sk_nnz, p->skC_ptr_d, p->skC_elem_d, p->skC_ab_d, p->sk_w_d, mm, p->skMc_val_d);
+  k_csr_diag<<<(unsigned)((nG + kBlock - 1) / kBlock), kBlock, 0, p->stream>>>(
+      nG, p->skL_rowptr_d, p->skL_col_d, p->skMc_val_d, p->skMcdiag_d);
   if (hipGetLastError() != hipSuccess) return EDD_EHIP;
   p->sk_state = weighting;
   return EDD_OK;
@@ -1211,19 +1305,52 @@ struct PC {
 
   // One Lanczos operator step on q: w = L^{-1} M q by the face-block PCG
   // (inverse Lanczos) or w = M^{-1} L q (forward Lanczos, no inner solve);
-  // t is work space.
-  int lanczos_operator(const double *q, double *t, double *w, bool forward, double tol,
-                       int maxit, edd_solve_stats *st) {
+  // with the consistent mass, mq = M q is given and M^{-1} is the Chebyshev
+  // iteration; t is work space.
+  int lanczos_operator(const double *q, const double *mq, double *t, double *w, bool forward,
+                       double tol, int maxit, edd_solve_stats *st) {
     if (forward) {
       spmv(q, t);
-      k_cscale<D><<<g1, kBlock, 0, p->stream>>>(nG, p->scal_d, 0, 3, p->skM_d, t, w);
+      if (mq) mass_solve(t, w);
+      else k_cscale<D><<<g1, kBlock, 0, p->stream>>>(nG, p->scal_d, 0, 3, p->skM_d, t, w);
       return EDD_OK;
     }
-    k_dscale<D><<<g1, kBlock, 0, p->stream>>>(nG, p->skM_d, q, t);
+    if (!mq) {
+      k_dscale<D><<<g1, kBlock, 0, p->stream>>>(nG, p->skM_d, q, t);
+      mq = t;
+    }
     int its = 0;
-    int rc = inner_pcg(t, w, tol, maxit, &its);
+    int rc = inner_pcg(mq, w, tol, maxit, &its);
     if (st) st->inner_iterations += its;
     return rc;
+  }
+
+  // y = M x, the consistent skeleton mass
+  void mass_apply(const double *x, double *y) {
+    k_spmv<D><<<g1, kBlock, 0, p->stream>>>(nG, p->skL_rowptr_d, p->skL_col_d, p->skMc_val_d,
+                                             x, y);
+  }
+
+  // x ~ M^{-1} b for the consistent mass: a fixed number of Chebyshev steps
+  // (no host synchronisation), enough for an M-norm error bound of 1e-12
+  // from the spectrum bounds of diag(M)^{-1} M (error factor
+  // 2 s^k / (1 + s^{2k}), s = (sqrt(kappa) - 1) / (sqrt(kappa) + 1))
+  void mass_solve(const double *b, double *x) {
+    double *r = p->pc_v_d[2], *d0 = p->pc_v_d[7], *d1 = p->pc_v_d[8];
+    const double lo = p->sk_cheb_lo, hi = p->sk_cheb_hi;
+    const double th = 0.5 * (hi + lo), de = 0.5 * (hi - lo);
+    const double sk = std::sqrt(hi / lo), sg = (sk - 1.0) / (sk + 1.0);
+    const int steps = std::min(200, (int)std::ceil(std::log(2.0 / 1e-12) / std::log(1.0 / sg)));
+    k_cheb_init<D><<<g1, kBlock, 0, p->stream>>>(nG, p->skMcdiag_d, 1.0 / th, b, x, r, d0);
+    double rho = de / th;
+    for (int it = 0; it < steps; ++it) {
+      const double rn = 1.0 / (2.0 * th / de - rho);
+      k_cheb_step<D><<<g1, kBlock, 0, p->stream>>>(nG, p->skL_rowptr_d, p->skL_col_d,
+                                                    p->skMc_val_d, p->skMcdiag_d, d0, d1, x, r,
+                                                    rn * rho, 2.0 * rn / de);
+      rho = rn;
+      std::swap(d0, d1);
+    }
   }
 
   void spmv(const double *x, double *y) {
@@ -1391,6 +1518,54 @@ void tridiag_power(int k, const double *alpha, const double *beta, int fkind, do
 // Fixed number of Lanczos steps and inner iterations; every scalar stays on
 // the device (no host synchronisation), so the whole application is one
 // asynchronous stream of kernels.
+// Lanczos basis Q and, for the consistent mass, MQ = M Q: kk vectors each
+int ensure_basis(edd_problem *p, int kk) {
+  if (p->pc_kcap >= kk) return EDD_OK;
+  const size_t bytes = sizeof(double) * p->n_gamma * p->g.dim * kk;
+  double *Q = (double *)dev_alloc(p, bytes), *MQ = (double *)dev_alloc(p, bytes);
+  if (!Q || !MQ) return EDD_ENOMEM;
+  p->pc_Q_d = Q;
+  p->pc_MQ_d = MQ;
+  p->pc_kcap = kk;
+  return EDD_OK;
+}
+
+// The start of the Lanczos process in the M inner product: b = M^{-1} r,
+// P_B0 = |b|_M^2, q_0 = b / |b|_M into Q; with the consistent mass |b|_M^2 =
+// b.r and M q_0 = r / |b|_M into MQ.  t receives b.
+template <int D>
+void lanczos_start(PC<D> &pc, bool cm, const double *r, double *t, double *Q, double *MQ) {
+  edd_problem *p = pc.p;
+  if (cm) {
+    pc.mass_solve(r, t);
+    pc.cdots(1, t, r, nullptr, nullptr, nullptr, P_B0, 0);
+    k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(pc.nG, p->scal_d, P_B0, 1, nullptr, r, MQ);
+  } else {
+    k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(pc.nG, p->scal_d, 0, 3, p->skM_d, r, t);
+    pc.cdots(1, t, t, nullptr, nullptr, p->skM_d, P_B0, 0);
+  }
+  k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(pc.nG, p->scal_d, P_B0, 1, nullptr, t, Q);
+}
+
+// The M inner products of a Lanczos step.  Lumped M: weighted dots.
+// Consistent M: dots with the stored M q_i (alpha, reorthogonalisation) and
+// |w|_M^2 = w.(M w) with M w into mw (the next M q up to the scale).
+template <int D>
+void lanczos_alpha(PC<D> &pc, bool cm, const double *qj, const double *mqj, const double *w) {
+  if (cm) pc.cdots(1, mqj, w, nullptr, nullptr, nullptr, P_A, 0);
+  else pc.cdots(1, qj, w, nullptr, nullptr, pc.p->skM_d, P_A, 0);
+}
+
+template <int D>
+void lanczos_beta(PC<D> &pc, bool cm, const double *w, double *mw) {
+  if (cm) {
+    pc.mass_apply(w, mw);
+    pc.cdots(1, w, mw, nullptr, nullptr, nullptr, P_B, 0);
+  } else {
+    pc.cdots(1, w, w, nullptr, nullptr, pc.p->skM_d, P_B, 0);
+  }
+}
+
 template <int D>
 int apply_device(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
                  edd_solve_stats *st) {
@@ -1398,37 +1573,36 @@ int apply_device(edd_problem *p, const double *r, double *z, const edd_solve_opt
   PC<D> pc{p, nG, (unsigned)((nG + kBlock - 1) / kBlock)};
   const double theta = o->theta >= 0.0 ? o->theta : p->theta_default;
   const int k = std::min(o->lanczos_kmax, 32);
-  if (p->pc_kcap < k + 1) {
-    double *Q = (double *)dev_alloc(p, sizeof(double) * nG * D * (k + 1));
-    if (!Q) return EDD_ENOMEM;
-    p->pc_Q_d = Q;
-    p->pc_kcap = k + 1;
-  }
+  if (int rc = ensure_basis(p, k + 1)) return rc;
   const int64_t n = nG * D;
-  double *Q = p->pc_Q_d;
+  const bool cm = o->mass_matrix == 1;
+  double *Q = p->pc_Q_d, *MQ = p->pc_MQ_d;
   double *w = p->pc_v_d[0], *t = p->pc_v_d[1];
-  k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, 0, 3, p->skM_d, r, t);
-  pc.cdots(1, t, t, nullptr, nullptr, p->skM_d, P_B0, 0);
-  k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_B0, 1, nullptr, t, Q);
+  lanczos_start<D>(pc, cm, r, t, Q, MQ);
   const bool fwd = pc_forward(o);
   for (int j = 0; j < k; ++j) {
-    double *qj = Q + (int64_t)j * n;
-    int rc = pc.lanczos_operator(qj, t, w, fwd, 0.0, o->inner_maxit, st);
+    double *qj = Q + (int64_t)j * n, *mqj = cm ? MQ + (int64_t)j * n : nullptr;
+    int rc = pc.lanczos_operator(qj, mqj, t, w, fwd, 0.0, o->inner_maxit, st);
     if (rc) return rc;
-    pc.cdots(1, qj, w, nullptr, nullptr, p->skM_d, P_A, 0);
+    lanczos_alpha<D>(pc, cm, qj, mqj, w);
     k_lanczos3<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, qj,
                                                    j > 0 ? Q + (int64_t)(j - 1) * n : nullptr, w);
     unsigned g = grid_for(nG);
     if (g > 128) g = 128;
-    k_cwindow_dots<D><<<g, kBlock, 0, p->stream>>>(nG, j + 1, Q, w, p->skM_d, p->partials_d);
+    k_cwindow_dots<D><<<g, kBlock, 0, p->stream>>>(nG, j + 1, cm ? MQ : Q, w,
+                                                   cm ? nullptr : p->skM_d, p->partials_d);
     k_reduce<<<(j + 1) * D, kBlock, 0, p->stream>>>(p->partials_d, (int)g, (j + 1) * D,
                                                     p->scal_d + P_H);
     k_ccombine<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, j + 1, Q, p->scal_d + P_H, 1.0, -1.0, w);
-    pc.cdots(1, w, w, nullptr, nullptr, p->skM_d, P_B, 0);
+    lanczos_beta<D>(pc, cm, w, t);
     k_store_ab<<<1, 64, 0, p->stream>>>(p->scal_d, j, D);
-    if (j + 1 < k)
+    if (j + 1 < k) {
       k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_B, 1, nullptr, w,
                                                    Q + (int64_t)(j + 1) * n);
+      if (cm)
+        k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_B, 1, nullptr, t,
+                                                     MQ + (int64_t)(j + 1) * n);
+    }
     if (st) st->lanczos_steps++;
   }
   k_lanczos_coef<<<1, 64, 0, p->stream>>>(p->scal_d, k, D, pc_fkind(o), 1.0 - theta);
@@ -1447,18 +1621,14 @@ int apply_graph(edd_problem *p, const double *r, double *z, const edd_solve_opts
   const int64_t nG = p->n_gamma;
   const int k = std::min(o->lanczos_kmax, 32);
   const double theta = o->theta >= 0.0 ? o->theta : p->theta_default;
-  const PcGraphKey key{r, z, k, o->inner_maxit, o->interface_weighting ? 1 : 0, theta, o->pc_form};
+  const PcGraphKey key{r,     z,           k, o->inner_maxit, o->interface_weighting ? 1 : 0,
+                       theta, o->pc_form, o->mass_matrix};
   if (!p->pc_graph || !(p->pc_graph_key == key)) {
     if (p->pc_graph) {
       hipGraphExecDestroy(p->pc_graph);
       p->pc_graph = nullptr;
     }
-    if (p->pc_kcap < k + 1) {  // allocate before capturing
-      double *Q = (double *)dev_alloc(p, sizeof(double) * nG * D * (k + 1));
-      if (!Q) return EDD_ENOMEM;
-      p->pc_Q_d = Q;
-      p->pc_kcap = k + 1;
-    }
+    if (int rc = ensure_basis(p, k + 1)) return rc;  // allocate before capturing
     if (!p->cap_stream &&
         hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
       p->cap_stream = nullptr;
@@ -1502,23 +1672,17 @@ int apply_t(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
   PC<D> pc{p, nG, (unsigned)((nG + kBlock - 1) / kBlock)};
   const double theta = o->theta >= 0.0 ? o->theta : p->theta_default;
   const int kmax = o->lanczos_kmax;
-  if (p->pc_kcap < kmax + 1) {
-    double *Q = (double *)dev_alloc(p, sizeof(double) * nG * D * (kmax + 1));
-    if (!Q) return EDD_ENOMEM;
-    p->pc_Q_d = Q;
-    p->pc_kcap = kmax + 1;
-  }
+  if (int rc = ensure_basis(p, kmax + 1)) return rc;
   const int64_t n = nG * D;
-  double *Q = p->pc_Q_d;
+  const bool cm = o->mass_matrix == 1;
+  double *Q = p->pc_Q_d, *MQ = p->pc_MQ_d;
   double *w = p->pc_v_d[0], *t = p->pc_v_d[1];
   // b = M^{-1} r ; beta0 = |b|_M ; q0 = b / beta0
-  k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, 0, 3, p->skM_d, r, t);
-  pc.cdots(1, t, t, nullptr, nullptr, p->skM_d, P_B0, 0);
+  lanczos_start<D>(pc, cm, r, t, Q, MQ);
   int rc = read_scalars(p, P_B0, D);
   if (rc) return rc;
   double beta0[3] = {0, 0, 0};
   for (int c = 0; c < D; ++c) beta0[c] = std::sqrt(std::max(0.0, p->scal_h[P_B0 + c]));
-  k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_B0, 1, nullptr, t, Q);
   std::vector<double> alpha[3], beta[3], yprev[3], ycur[3];
   bool conv[3] = {false, false, false};
   for (int c = 0; c < D; ++c) conv[c] = beta0[c] == 0.0;
@@ -1526,25 +1690,26 @@ int apply_t(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
   const bool fwd = pc_forward(o);
   const int fkind = pc_fkind(o);
   for (int j = 0; j < kmax; ++j) {
-    double *qj = Q + (int64_t)j * n;
+    double *qj = Q + (int64_t)j * n, *mqj = cm ? MQ + (int64_t)j * n : nullptr;
     // w = L^{-1} M q_j (inverse Lanczos) or M^{-1} L q_j (forward)
-    rc = pc.lanczos_operator(qj, t, w, fwd, o->inner_tol, o->inner_maxit, st);
+    rc = pc.lanczos_operator(qj, mqj, t, w, fwd, o->inner_tol, o->inner_maxit, st);
     if (rc) return rc;
     // alpha = <q_j, w>_M ; w -= alpha q_j + beta q_{j-1}
-    pc.cdots(1, qj, w, nullptr, nullptr, p->skM_d, P_A, 0);
+    lanczos_alpha<D>(pc, cm, qj, mqj, w);
     k_lanczos3<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, qj,
                                                    j > 0 ? Q + (int64_t)(j - 1) * n : nullptr, w);
     // full reorthogonalisation against q_0..q_j in the M inner product
     {
       unsigned g = grid_for(nG);
       if (g > 128) g = 128;
-      k_cwindow_dots<D><<<g, kBlock, 0, p->stream>>>(nG, j + 1, Q, w, p->skM_d, p->partials_d);
+      k_cwindow_dots<D><<<g, kBlock, 0, p->stream>>>(nG, j + 1, cm ? MQ : Q, w,
+                                                     cm ? nullptr : p->skM_d, p->partials_d);
       k_reduce<<<(j + 1) * D, kBlock, 0, p->stream>>>(p->partials_d, (int)g, (j + 1) * D,
                                                       p->scal_d + P_H);
       k_ccombine<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, j + 1, Q, p->scal_d + P_H, 1.0,
                                                      -1.0, w);
     }
-    pc.cdots(1, w, w, nullptr, nullptr, p->skM_d, P_B, 0);
+    lanczos_beta<D>(pc, cm, w, t);
     rc = read_scalars(p, P_A, 6);
     if (rc) return rc;
     k = j + 1;
@@ -1582,6 +1747,9 @@ int apply_t(edd_problem *p, const double *r, double *z, const edd_solve_opts *o,
                    hipMemcpyHostToDevice, p->stream);
     k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_H, 0, nullptr, w,
                                                  Q + (int64_t)(j + 1) * n);
+    if (cm)
+      k_cscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->scal_d, P_H, 0, nullptr, t,
+                                                   MQ + (int64_t)(j + 1) * n);
   }
   // z = Q_k y
   for (int i = 0; i < k; ++i)
@@ -1603,6 +1771,8 @@ static int skeleton_op_t(edd_problem *p, int which, const double *x, double *y,
   if (which == 0) pc.spmv(x, y);
   else if (which == 1) k_dscale<D><<<pc.g1, kBlock, 0, p->stream>>>(nG, p->skM_d, x, y);
   else if (which == 2) pc.face_precond(x, y);
+  else if (which == 4) pc.mass_apply(x, y);
+  else if (which == 5) pc.mass_solve(x, y);
   else {
     int its = 0;
     int rc = pc.inner_pcg(x, y, tol, maxit, &its);

@@ -86,6 +86,7 @@ class SolveOpts(ctypes.Structure):
         ("use_graphs", ctypes.c_int),
         ("pc_form", ctypes.c_int),
         ("learned_correction", ctypes.c_int),
+        ("mass_matrix", ctypes.c_int),
     ]
 
 
@@ -611,7 +612,8 @@ class Problem:
         return out
 
     def skeleton_op(self, which, x, weighting=1, tol=1e-12, maxit=1000, out=None):
-        """which: 0 L, 1 M (lumped), 2 face-block preconditioner, 3 PCG solve."""
+        """which: 0 L, 1 M (lumped), 2 face-block preconditioner, 3 PCG solve,
+        4 M (consistent), 5 M^{-1} (consistent, Chebyshev)."""
         if out is None:
             out = torch.empty_like(x)
         n = self.n_gamma_dofs

@@ -146,3 +146,41 @@ def test_weighted_htheta_helps_heterogeneous_interface():
     _, its_w, _ = krylov.schur_pcg(p, precond="htilde_lumped", theta=0.5, tol=1e-8,
                                    weighted=True)
     assert its_w < 0.6 * its_u
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_consistent_mass_integrates_products_exactly(dim):
+    """The consistent skeleton mass is the Gram matrix of the piecewise
+    (bi)linear functions on the skeleton: for the nodal values u of x and of
+    x*y, which lie in that space on every cut line or plane and vanish on the
+    clamped face x = 0 (so the removed rows carry zeros), u^T M u is the
+    integral of u^2 over the skeleton.  The integrals here are summed over the
+    cuts in closed form.  The lumped mass misses them (it is exact only for
+    linear integrands)."""
+    if dim == 2:
+        p = w.cantilever2d(24, 16, block=8)
+    else:
+        p = w.cantilever3d(8, 8, 6, cuts=(w.even_cuts(8, 4), w.even_cuts(8, 4),
+                                          np.array([0, 3, 6])))
+    M, _, g = iface.skeleton_matrices(p)
+    Ml, _, _ = iface.skeleton_matrices(p, lumped=True)
+    nn = [n + 1 for n in p.nel]
+    x = (g % nn[0]).astype(float)
+    y = ((g // nn[0]) % nn[1]).astype(float)
+    cx, cy = p.cuts[0][1:-1], p.cuts[1][1:-1]
+    nx, ny = p.nel[0], p.nel[1]
+    if dim == 2:
+        # vertical lines x = c (0 <= y <= ny), horizontal lines y = c
+        int_x2 = sum(c * c * ny for c in cx) + len(cy) * nx ** 3 / 3
+        int_xy2 = sum(c * c * ny ** 3 / 3 for c in cx) + sum(c * c * nx ** 3 / 3 for c in cy)
+    else:
+        nz, cz = p.nel[2], p.cuts[2][1:-1]
+        # planes x = c (y, z free), y = c (x, z free), z = c (x, y free)
+        int_x2 = (sum(c * c * ny * nz for c in cx) + len(cy) * nx ** 3 / 3 * nz
+                  + len(cz) * nx ** 3 / 3 * ny)
+        int_xy2 = (sum(c * c * ny ** 3 / 3 * nz for c in cx)
+                   + sum(c * c * nx ** 3 / 3 * nz for c in cy)
+                   + len(cz) * (nx ** 3 / 3) * (ny ** 3 / 3))
+    for u, exact in ((x, int_x2), (x * y, int_xy2)):
+        assert u @ (M @ u) == pytest.approx(exact, rel=1e-13)
+        assert abs(u @ (Ml @ u) - exact) > 1e-6 * exact
