@@ -135,3 +135,35 @@ def test_consistent_mass_device_resident_graph_and_solve(dim):
     with pytest.raises(edd.EddError):
         prob.apply_precond(to_cuda(r), precond=edd.PC_HTHETA, mass_matrix=2)
     prob.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_consistent_mass_in_captured_iterations_and_batch(dim):
+    """use_graphs = 8 (the interface iterations replayed from a captured
+    graph, the Chebyshev M^{-1} inside it) against the host-driven loop, and
+    the batch entry point against single solves, both with the consistent
+    mass."""
+    require_gpu()
+    from paper_1501_06211_amd import edd
+    p = _small2d() if dim == 2 else _small3d()
+    prob = make_problem(p)
+    f = to_cuda(p.f)
+    uref = fe.solve_direct(p)
+    u0, s0 = prob.solve(f, tol=1e-10, maxit=3000, mass_matrix=1)
+    u0 = to_np(u0)
+    u1, s1 = prob.solve(f, tol=1e-10, maxit=3000, mass_matrix=1, use_graphs=8)
+    u1 = to_np(u1)
+    print(f"{dim}D consistent M: host loop {s0['iterations']} its, graph {s1['iterations']} its")
+    assert abs(s1["iterations"] - s0["iterations"]) <= 16
+    assert np.linalg.norm(u1 - u0) <= 1e-9 * np.linalg.norm(u0)
+    assert np.linalg.norm(u1 - uref) <= 1e-8 * np.linalg.norm(uref)
+    prob2 = make_problem(p)
+    import torch
+    outs = [torch.zeros_like(f), torch.zeros_like(f)]
+    status, stats = edd.solve_batch([prob, prob2], [f, f], outs, tol=1e-10, maxit=3000,
+                                    mass_matrix=1)
+    assert status == edd.OK
+    for u in outs:
+        assert np.array_equal(to_np(u), u0)
+    prob.close()
+    prob2.close()
