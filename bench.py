@@ -159,8 +159,10 @@ def time_path(prob, E, f, u, opts, steps, warmup, timing=False):
     stats = []
     t0 = time.perf_counter()
     for k in range(steps):
+        ts = time.perf_counter()
         prob.set_element_moduli(E)
-        _, st = prob.solve(f, u, **opts)
+        _, st = prob.solve(f, u, **opts)  # synchronises before returning
+        st["step_ms"] = (time.perf_counter() - ts) * 1e3
         stats.append(st)
         print(f"[bench]   step {k}: its={st['iterations']} outer={st['outer_iterations']} "
               f"res={st['rel_residual']:.2e} {st['t_total_ms']:.1f} ms (solve)",
@@ -719,7 +721,13 @@ def main():
     leg_out = {}
     for leg, r in res.items():
         s = r["stats"][-1]
-        d = {"ms_per_step": round(r["ms"], 3), "iterations": s["iterations"],
+        step_ms = sorted(x["step_ms"] for x in r["stats"])
+        d = {"ms_per_step": round(r["ms"], 3),
+             "step_ms_min_median_max": [round(step_ms[0], 2),
+                                        round(float(np.median(step_ms)), 2),
+                                        round(step_ms[-1], 2)],
+             "solve_ms_per_step": [round(x["t_total_ms"], 2) for x in r["stats"]],
+             "iterations": s["iterations"],
              "rel_residual": s["rel_residual"], "compliance": s["compliance"],
              "flags": s["flags"], "factors": LEG_OPTS[leg][0]}
         if LEG_OPTS[leg][1].get("mixed"):
