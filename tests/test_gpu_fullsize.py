@@ -8,8 +8,9 @@ reference (tests/golden, written by make_reference.py: the oracle's Schur
 route refined in long double to rel.res 3.6e-15), the oracle's
 element-by-element K apply and its residual of the GPU solution, and
 interior solves of sampled subdomains against the oracle's sparse
-factorisation of that block, and the interface preconditioner on the whole
-83,178-node skeleton against the oracle's inverse Lanczos."""
+factorisation of that block, the S apply for vectors supported on one
+interface face, and the interface preconditioner on the whole 83,178-node
+skeleton against the oracle's inverse Lanczos."""
 import json
 import os
 
@@ -184,4 +185,55 @@ def test_3d_128x64x64_preconditioner_against_oracle_lanczos(mass):
     print(f"3D 128x64x64 preconditioner, mass {mass}: 3 exact-solve steps vs oracle {err:.2e}; "
           f"benchmark's 3 x 4 form vs oracle {errb:.2e}")
     assert err <= 1e-8
+    prob.close()
+
+
+def _interior_solve(wk, sid, b):
+    """K_{I_i I_i}^{-1} b on subdomain sid's interior dofs (b full-length;
+    only those entries read), by the oracle's sparse factorisation of the
+    subdomain's own free system; full-length result, zero elsewhere."""
+    sub, lo = _sub_block(wk, sid)
+    Kff, _ = fe.free_system(sub)
+    nn = [n + 1 for n in wk.nel]
+    snn = [n + 1 for n in sub.nel]
+    dofs = np.flatnonzero(~fe.dirichlet_dof_mask(sub))
+    ln, comp = dofs // 3, dofs % 3
+    lx, ly, lz = ln % snn[0], (ln // snn[0]) % snn[1], ln // (snn[0] * snn[1])
+    gdof = 3 * ((lo[0] + lx) + nn[0] * ((lo[1] + ly) + nn[1] * (lo[2] + lz))) + comp
+    out = np.zeros(wk.ndof)
+    out[gdof] = spla.spsolve(Kff.tocsc(), b[gdof])
+    return out
+
+
+@pytest.mark.parametrize("layer", [0, 2])
+def test_3d_128x64x64_S_apply_on_sampled_faces(layer):
+    """S v at full size, in the benchmark's launch configuration, for v
+    supported inside one interface face (x = 48 between the subdomains at
+    x-blocks 2 and 3, y-block 1, z-block `layer`; layer 0 holds the 16^3
+    subdomains whose interiors are dissected).  Then K [0; v] touches only
+    those two interiors, and the oracle forms S v = (K [-K_II^{-1}
+    (K [0; v])_I ; v])_Gamma with two sparse interior solves and two
+    element-by-element K applies, compared on every interface dof."""
+    require_gpu()
+    from oracle import dd
+    wk = w.cantilever3d_simp_128x64x64()
+    prob = _problem(wk)
+    nn = [n + 1 for n in wk.nel]
+    zc = wk.cuts[2]
+    ys, zs = np.arange(17, 32), np.arange(zc[layer] + 1, zc[layer + 1])
+    face = (48 + nn[0] * (ys[:, None] + nn[1] * zs[None, :])).reshape(-1)
+    rng = np.random.default_rng(11 + layer)
+    v = np.zeros(wk.ndof)
+    v[(3 * face[:, None] + np.arange(3)).reshape(-1)] = rng.standard_normal(3 * len(face))
+    y = fe.apply_K_elementwise(wk, v)
+    nb = [len(c) - 1 for c in wk.cuts]
+    x = sum(_interior_solve(wk, sx + nb[0] * (1 + nb[1] * layer), y) for sx in (2, 3))
+    Sv = fe.apply_K_elementwise(wk, v - x)
+    g = np.flatnonzero(dd.classify(wk) == dd.GAMMA)
+    gd = (3 * g[:, None] + np.arange(3)).reshape(-1)
+    ref = Sv[gd]
+    out = to_np(prob.apply_S(to_cuda(v[gd])))
+    err = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+    print(f"3D 128x64x64 S v on a face of z-layer {layer} ({len(face)} nodes): rel err {err:.2e}")
+    assert err <= 1e-12
     prob.close()
