@@ -163,3 +163,37 @@ def test_table3_trend():
     print(f"  N=16, h 1/16 -> 1/64: iterations x{growth_h:.2f} with Hhat_theta, "
           f"x{growth_i:.2f} with S~ = I")
     assert growth_h < 1.6 and growth_h < growth_i
+
+
+def test_energies_and_oc_step_at_full_size():
+    """One fixed-point step's kernels at the size of the Section 5 run
+    (2D 1024x512, 2,048 subdomains): element energies of a solved
+    displacement and the OC update with its volume multiplier, against the
+    oracle on every element."""
+    require_gpu()
+    p = w.cantilever2d(1024, 512)  # 16 x 16-element subdomains
+    prob = make_problem(p)
+    rho = np.full(p.n_el, 0.5)
+    prob.set_element_moduli(to_cuda(topopt.moduli(rho, 3.0, 1e-3)))
+    u, st = prob.solve(to_cuda(p.f), tol=1e-8, maxit=8000)
+    un = to_np(u)
+    s = to_np(prob.element_energies(u))
+    s_ref = topopt.element_energies(p, un)
+    # a solved displacement is smooth: u_e^T K0 u_e is a small difference of
+    # terms of the size of |u_e|^T |K0| |u_e|, and both sides round each of
+    # the 64 products, so the bar is the forward error bound of that sum
+    K0 = fe.element_stiffness(p.dim, p.nu)
+    ue = np.where(fe.dirichlet_dof_mask(p), 0.0, un)[fe.element_dofs(p)]
+    scale = np.einsum("ei,ij,ej->e", np.abs(ue), np.abs(K0), np.abs(ue))
+    es = np.max(np.abs(s - s_ref) / (128 * np.finfo(float).eps * scale))
+    V = 0.5 * p.n_el
+    g = topopt.sensitivity_weights(rho, 3.0, 1e-3) * s_ref
+    ref, lam_ref = topopt.oc_update(rho, g, V)
+    new, _, res = prob.oc_update(to_cuda(rho), to_cuda(s_ref), V, penal=3.0, emin=1e-3)
+    dr = np.abs(to_np(new) - ref).max()
+    print(f"1024x512: {st['iterations']} its; energies at {es:.2f} of the rounding bound; OC lambda "
+          f"{res['lambda']:.15e} (oracle {lam_ref:.15e}), max |drho| {dr:.2e}")
+    assert es <= 1.0 and dr <= 1e-10
+    assert abs(res["lambda"] - lam_ref) <= 1e-9 * lam_ref
+    assert abs(res["volume"] - V) <= 1e-9 * V
+    prob.close()
