@@ -256,3 +256,63 @@ def test_3d_128x64x64_fgmres_on_K_against_reference():
     assert st["rel_residual"] <= 1e-11
     assert err <= 1e-8 and cerr <= 1e-10
     prob.close()
+
+
+def _sub_block_2d(wk, sid):
+    """2D subdomain sid as its own problem with its cut faces clamped."""
+    nb = [len(c) - 1 for c in wk.cuts]
+    b = [sid % nb[0], sid // nb[0]]
+    lo = [int(wk.cuts[a][b[a]]) for a in range(2)]
+    hi = [int(wk.cuts[a][b[a] + 1]) for a in range(2)]
+    E2 = wk.E.reshape(wk.nel[1], wk.nel[0])
+    Es = E2[lo[1]:hi[1], lo[0]:hi[0]].reshape(-1)
+    dims = [hi[a] - lo[a] for a in range(2)]
+    sub = w.cantilever2d(*dims, cuts=([0, dims[0]], [0, dims[1]]), E=Es)
+    clamp = 0
+    for a in range(2):
+        if lo[a] > 0 or (wk.clamp >> (2 * a)) & 1:
+            clamp |= 1 << (2 * a)
+        if hi[a] < wk.nel[a] or (wk.clamp >> (2 * a + 1)) & 1:
+            clamp |= 1 << (2 * a + 1)
+    sub.clamp = clamp
+    return sub, lo
+
+
+def test_2d_512x256_S_apply_both_routes_on_a_sampled_edge():
+    """S v at the 2D benchmark size (512 subdomains) through the interior
+    factors and through the explicit local Schur complements S_i, for v
+    inside one interface edge (x = 48 between x-blocks 2 and 3, y-block 3):
+    against the oracle's S v from two sparse interior solves and two
+    element-by-element K applies."""
+    require_gpu()
+    from oracle import dd
+    wk = w.cantilever2d_simp_512x256()
+    prob = _problem(wk)
+    nn = [n + 1 for n in wk.nel]
+    edge = 48 + nn[0] * np.arange(49, 64)
+    v = np.zeros(wk.ndof)
+    v[(2 * edge[:, None] + np.arange(2)).reshape(-1)] = \
+        np.random.default_rng(13).standard_normal(2 * len(edge))
+    y = fe.apply_K_elementwise(wk, v)
+    x = np.zeros(wk.ndof)
+    nb = [len(c) - 1 for c in wk.cuts]
+    for sx in (2, 3):
+        sub, lo = _sub_block_2d(wk, sx + nb[0] * 3)
+        Kff, _ = fe.free_system(sub)
+        snn = [n + 1 for n in sub.nel]
+        dofs = np.flatnonzero(~fe.dirichlet_dof_mask(sub))
+        ln, comp = dofs // 2, dofs % 2
+        gdof = 2 * ((lo[0] + ln % snn[0]) + nn[0] * (lo[1] + ln // snn[0])) + comp
+        x[gdof] = spla.spsolve(Kff.tocsc(), y[gdof])
+    Sv = fe.apply_K_elementwise(wk, v - x)
+    g = np.flatnonzero(dd.classify(wk) == dd.GAMMA)
+    gd = (2 * g[:, None] + np.arange(2)).reshape(-1)
+    ref = Sv[gd]
+    for mode in (0, 1):
+        prob.set_s_apply(mode)
+        out = to_np(prob.apply_S(to_cuda(v[gd])))
+        err = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+        print(f"2D 512x256 S v on an edge, {'explicit S_i' if mode else 'interior factors'}: "
+              f"rel err {err:.2e}")
+        assert err <= 1e-12
+    prob.close()
