@@ -178,7 +178,10 @@ __global__ __launch_bounds__(256) void k_apply_tiled(
   constexpr int EX = TX + 1, EY = TY + 1, EZ = (D == 3) ? TZ + 1 : 1;
   constexpr int NC = (D == 3) ? 8 : 4;
   constexpr int ND = D * NC;
-  __shared__ double us[HX * HY * HZ * D];
+  // one plane per component: neighbouring threads read neighbouring words
+  // (a node-interleaved layout put them 8 * D bytes apart, into the same banks)
+  constexpr int NQ = HX * HY * HZ;
+  __shared__ double us[NQ * D];
   __shared__ double Es[EX * EY * EZ];
   const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY, k0 = blockIdx.z * TZ;
 #pragma unroll 1
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(256) void k_apply_tiled(
       for (int c = 0; c < D; ++c) v[c] = 0.0;
     }
 #pragma unroll
-    for (int c = 0; c < D; ++c) us[q * D + c] = v[c];
+    for (int c = 0; c < D; ++c) us[c * NQ + q] = v[c];
   }
 #pragma unroll 1
   for (int q = threadIdx.x; q < EX * EY * EZ; q += 256) {
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(256) void k_apply_tiled(
                          HX * ((ty + sy_ + corner_y(b)) +
                                HY * (D == 3 ? tz + sz + corner_z(b) : 0));
 #pragma unroll
-          for (int c = 0; c < D; ++c) xe[D * b + c] = us[hq * D + c];
+          for (int c = 0; c < D; ++c) xe[D * b + c] = us[c * NQ + hq];
         }
 #pragma unroll
         for (int c = 0; c < D; ++c) {
