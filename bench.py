@@ -69,11 +69,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="3d",
-                    choices=["3d", "2d", "small", "batch", "sequence", "topopt"],
+                    choices=["3d", "2d", "small", "batch", "sequence", "sequence2d", "topopt"],
                     help="batch: the 64 uneven problems solved concurrently "
                          "(solves/s and per-problem latency); sequence: a 3D "
                          "128x64x64 density sequence, network trained on the "
-                         "first solves, held-out solves timed plain vs learned; "
+                         "first solves, held-out solves timed plain vs learned "
+                         "(sequence2d: the same on the 2D 1024x512 cantilever with "
+                         "2048 subdomains, the fields of to_sequence_2d); "
                          "topopt: the topology-optimisation loop (OC update, adaptive "
                          "tolerance) on the 2D 1024x512 cantilever with 2048 subdomains, "
                          "and the mesh/subdomain sweep of the paper's Table 3")
@@ -333,9 +335,10 @@ def run_batch(args):
     print(json.dumps(out))
 
 
-def run_sequence(args):
-    """Topology-optimisation-like sequence on the 3D 128x64x64 cantilever:
-    densities blended 10% per step toward a fresh seeded field and
+def run_sequence(args, dim=3):
+    """Topology-optimisation-like sequence on the 3D 128x64x64 cantilever
+    (dim 3) or the 2D 1024x512 cantilever with 16x16-element subdomains
+    (dim 2): densities blended 10% per step toward a fresh seeded field and
     thresholded (E = 1e-3 + rho^3).  The first solves (warm-started from the
     previous solution) train the correction network; on the held-out steps
     each solve is timed from the same warm start plain, with the learned
@@ -347,10 +350,16 @@ def run_sequence(args):
     from paper_1501_06211_amd import edd, learned
 
     torch.cuda.set_device(0)
-    base = workloads.cantilever3d_simp_128x64x64()
     t0 = time.perf_counter()
-    seq = [torch.tensor(E, device="cuda")
-           for E in workloads.to_sequence_3d(args.train + args.test, 128, 64, 64, ell=8.0)]
+    if dim == 3:
+        base = workloads.cantilever3d_simp_128x64x64()
+        fields = workloads.to_sequence_3d(args.train + args.test, 128, 64, 64, ell=8.0)
+        wl_name = "cantilever3d_sequence_128x64x64"
+    else:
+        base = workloads.cantilever2d(1024, 512, name="cantilever2d_1024x512")
+        fields = workloads.to_sequence_2d(args.train + args.test, 1024, 512)
+        wl_name = "cantilever2d_sequence_1024x512"
+    seq = [torch.tensor(E, device="cuda") for E in fields]
     print(f"[bench] sequence of {len(seq)} fields in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     prob = edd.Problem.from_workload(base)
@@ -359,7 +368,7 @@ def run_sequence(args):
     prob.autotune()
     prob.cnn_setup(32)
     prob.cnn_set_params(learned.flatten_params(
-        workloads.cnn_initial_weights(3, 4, 32, 3, seed=1)))
+        workloads.cnn_initial_weights(dim, dim + 1, 32, dim, seed=1)))
     opts = dict(tol=args.tol, maxit=5000)
     t0 = time.perf_counter()
     tr, u_prev = learned.warm_start_solves(
@@ -397,13 +406,14 @@ def run_sequence(args):
     mean = {n: float(np.mean([r[n][0] for r in rows])) for n in rows[0]}
     its = {n: float(np.mean([r[n][1] for r in rows])) for n in rows[0]}
     out = {
-        "metric": "time to rel.res 1e-8 on held-out steps of a 3D 128x64x64 density sequence: "
-                  "plain vs learned vs learned+mixed",
+        "metric": "time to rel.res 1e-8 on held-out steps of a %s density sequence: "
+                  "plain vs learned vs learned+mixed" % ("3D 128x64x64" if dim == 3 else
+                                                         "2D 1024x512"),
         "value": round(mean["learned_mixed"], 2), "unit": "ms", "n_gpus": 1,
         "steps": args.test, "warmup": 0, "ms_per_step": round(mean["learned_mixed"], 2),
         "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
         "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": "cantilever3d_sequence_128x64x64", "train_solves": args.train,
+        "config": {"workload": wl_name, "train_solves": args.train,
                    "test_solves": args.test, "epochs": args.epochs, "tol": args.tol,
                    "parallelism": "single GPU"},
         "mean_ms": {n: round(v, 2) for n, v in mean.items()},
@@ -616,8 +626,8 @@ def main():
         PC_EXTRA["lanczos_kmax"] = args.lanczos_k
     if args.inner is not None:
         PC_EXTRA["inner_maxit"] = args.inner
-    if args.workload == "sequence":
-        run_sequence(args)
+    if args.workload in ("sequence", "sequence2d"):
+        run_sequence(args, dim=2 if args.workload == "sequence2d" else 3)
         return
     if args.workload == "batch":
         run_batch(args)

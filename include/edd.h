@@ -148,7 +148,12 @@ typedef struct edd_solve_opts {
                           /* EDD_MODE_RELAXED: relative residual at which    */
                           /* the S applies switch to FP32 factors            */
   int flexible_window; /* directions kept by the flexible Krylov (0 = all,   */
-                       /* capped at 256; 1 = short recurrence)               */
+                       /* up to 8192, or 256 for the captured iteration;    */
+                       /* 1 = short recurrence).  They are stored in blocks */
+                       /* of 256 vectors of 2 n_gamma dim doubles (the      */
+                       /* direction and its S image), allocated when the    */
+                       /* iteration first reaches them and kept until       */
+                       /* edd_destroy                                       */
   int interface_weighting; /* 0: M, L of the skeleton as in the paper;        */
                            /* 1: each skeleton element scaled by the mean     */
                            /*    modulus of its two neighbouring elements     */
@@ -161,7 +166,9 @@ typedef struct edd_solve_opts {
                       /* n >= 2: the interface iteration itself runs as      */
                       /* replays of a captured graph of n iterations (up to  */
                       /* 64; device-resident preconditioner, FP64 or mixed   */
-                      /* mode): the window comes from a device iteration     */
+                      /* mode, a window of at most 256 directions; a larger  */
+                      /* one runs the host-driven loop): the window comes    */
+                      /* from a device iteration                             */
                       /* index and a device flag marks convergence, read by  */
                       /* the host once per replay.  Up to the first         */
                       /* converged iteration the arithmetic is bitwise that  */

@@ -46,9 +46,8 @@ enum : int {
   S_BREAK = 8,  // set on the device by a breakdown step of the interface CG
   S_RRH = 9,    // 9..12: r.r of the last iterations (ring of kCheck)
   S_NETDROP = 13,  // set by a network step that gave no direction (dropped)
-  S_C_BASE = 16,
-  S_PQ_BASE = 16 + 256,
-  S_PC_BASE = 16 + 512,
+  S_C_BASE = 4096,  // window coefficients <z, q_j>, one per ring slot
+  S_PQ_BASE = 4096 + kMaxWindow,  // <p_j, q_j> per ring slot
   S_TOTAL = kScalTotal
 };
 
@@ -141,44 +140,63 @@ void apply_S(edd_problem *p, const double *v, double *y, int prec) {
   apply_S_with(p, v, y, prec, p->w_I[2]);
 }
 
-static int ensure_window(edd_problem *p, int cap) {
-  if (cap <= p->win_cap) return EDD_OK;
+// Ring slots [0, nslots) of the flexible-CG window: blocks of kWinBlock
+// directions (P) and their S images (Q), each allocated the first time the
+// iteration reaches it and kept until the handle is destroyed.
+static int ensure_window(edd_problem *p, int nslots) {
   const size_t nG = (size_t)p->n_gamma * p->g.dim;
-  double *P = (double *)dev_alloc(p, sizeof(double) * nG * cap);
-  double *Q = (double *)dev_alloc(p, sizeof(double) * nG * cap);
-  if (!P || !Q) return EDD_ENOMEM;
-  p->winP_d = P;
-  p->winQ_d = Q;
-  p->win_cap = cap;
+  while ((int)p->winP_blk.size() * kWinBlock < nslots) {
+    double *P = (double *)dev_alloc(p, sizeof(double) * nG * kWinBlock);
+    double *Q = (double *)dev_alloc(p, sizeof(double) * nG * kWinBlock);
+    if (!P || !Q) return EDD_ENOMEM;
+    p->winP_blk.push_back(P);
+    p->winQ_blk.push_back(Q);
+  }
   return EDD_OK;
 }
 
-// Orthogonalise z against the previous m directions of a ring buffer
-// (capacity cap, newest at slot (k-1) % cap) and write the result to out.
-static void window_orthogonalise(edd_problem *p, int64_t n, double *ringP,
-                                 double *ringQ, int cap, int k, int m,
-                                 const double *z, double *out, int cbase,
-                                 int dbase) {
+static double *win_slot(const std::vector<double *> &blk, int64_t n, int slot) {
+  return blk[slot / kWinBlock] + (int64_t)(slot % kWinBlock) * n;
+}
+
+// Directions the flexible CG keeps: the option if set; else one (plain CG)
+// for the identity preconditioner, kWinBlock for the captured iteration,
+// and all of them (up to kMaxWindow) otherwise.
+static int fcg_window(const edd_solve_opts *o) {
+  if (o->flexible_window > 0) return o->flexible_window;
+  if (o->precond == EDD_PC_IDENTITY) return 1;
+  return o->use_graphs >= 2 ? kWinBlock : kMaxWindow;
+}
+
+// Orthogonalise z against the m newest directions of the window ring
+// (capacity cap, direction j at slot j % cap, newest at (k-1) % cap) and
+// write the result to out.  The directions go oldest first, in runs of
+// consecutive slots inside one block (at most kWinBlock, what one window
+// kernel takes): every coefficient against z first, then the combines.
+static void window_orthogonalise(edd_problem *p, int64_t n, int cap, int k, int m,
+                                 const double *z, double *out, int cbase, int dbase) {
   if (m <= 0) {
     if (out != z) launch_copy(p, n, z, out);
     return;
   }
-  const int first = ((k - m) % cap + cap) % cap;
-  int segs[2][2];
-  int ns = 0;
-  if (first + m <= cap) {
-    segs[ns][0] = first; segs[ns][1] = m; ++ns;
-  } else {
-    segs[ns][0] = first; segs[ns][1] = cap - first; ++ns;
-    segs[ns][0] = 0; segs[ns][1] = m - (cap - first); ++ns;
+  constexpr int kMaxRuns = kMaxWindow / kWinBlock + 2;
+  int runs[kMaxRuns][2];
+  int nr = 0;
+  for (int t = 0; t < m && nr < kMaxRuns;) {
+    const int slot = (k - m + t) % cap;  // k >= m
+    const int len = std::min(std::min(m - t, cap - slot), kWinBlock - slot % kWinBlock);
+    runs[nr][0] = slot;
+    runs[nr][1] = len;
+    ++nr;
+    t += len;
   }
-  for (int s = 0; s < ns; ++s)
-    launch_window_dots(p, n, segs[s][1], ringQ + (int64_t)segs[s][0] * n, z,
-                       cbase + segs[s][0]);
+  for (int s = 0; s < nr; ++s)
+    launch_window_dots(p, n, runs[s][1], win_slot(p->winQ_blk, n, runs[s][0]), z,
+                       cbase + runs[s][0]);
   const double *src = z;
-  for (int s = 0; s < ns; ++s) {
-    launch_window_combine(p, n, segs[s][1], ringP + (int64_t)segs[s][0] * n,
-                          cbase + segs[s][0], dbase + segs[s][0], src, out);
+  for (int s = 0; s < nr; ++s) {
+    launch_window_combine(p, n, runs[s][1], win_slot(p->winP_blk, n, runs[s][0]),
+                          cbase + runs[s][0], dbase + runs[s][0], src, out);
     src = out;
   }
 }
@@ -263,16 +281,16 @@ static int fcg_graph_iterations(edd_problem *p, double *x, int prec, double tol_
           rc = precond_apply(p, r, z, &oc, nullptr, false);
           zp = z;
         }
-        launch_window_dots_dev(p, nG, cap, p->winQ_d, zp, S_C_BASE);
-        launch_window_combine_dev(p, nG, cap, p->winP_d, S_C_BASE, S_PQ_BASE, zp, pn);
+        launch_window_dots_dev(p, nG, cap, p->winQ_blk[0], zp, S_C_BASE);
+        launch_window_combine_dev(p, nG, cap, p->winP_blk[0], S_C_BASE, S_PQ_BASE, zp, pn);
         apply_S(p, pn, qn, prec);
         {
           const double *a[2] = {pn, pn}, *b[2] = {qn, r};
           launch_dots(p, nG, 2, a, b, S_PQCUR);
         }
         launch_cg_update(p, nG, S_PR, S_PQCUR, x, pn, r, qn, kSlotGRR, kSlotGPQ, S_BREAK);
-        launch_ring_store(p, nG, cap, pn, p->winP_d);
-        launch_ring_store(p, nG, cap, qn, p->winQ_d);
+        launch_ring_store(p, nG, cap, pn, p->winP_blk[0]);
+        launch_ring_store(p, nG, cap, qn, p->winQ_blk[0]);
         launch_iter_end(p, cap, S_PQ_BASE);
       }
       if (hipStreamEndCapture(p->cap_stream, &graph) != hipSuccess) rc = EDD_EHIP;
@@ -349,12 +367,13 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
   double rr = p->scal_h[S_RR];
   if (!std::isfinite(rr)) return EDD_EINVAL;
   const bool pc_identity = o->precond == EDD_PC_IDENTITY;
-  const int cap = std::max(1, std::min(window, 256));
-  rc = ensure_window(p, cap);
+  const int cap = std::max(1, std::min(window, kMaxWindow));
+  rc = ensure_window(p, std::min(cap, kWinBlock));
   if (rc) return rc;
   const bool pc_dev = pc_identity || (o->lanczos_tol <= 0.0 && o->inner_tol <= 0.0);
-  if (o->use_graphs >= 2 && pc_dev && relax_abs <= 0.0 && o->learned_correction <= 0 &&
-      std::sqrt(rr) > tol_abs) {
+  // the captured iteration keeps its ring in the first block
+  if (o->use_graphs >= 2 && cap <= kWinBlock && pc_dev && relax_abs <= 0.0 &&
+      o->learned_correction <= 0 && std::sqrt(rr) > tol_abs) {
     launch_fill(p, 1, 0.0, p->scal_d + S_BREAK);
     return fcg_graph_iterations(p, x, prec, tol_abs, o, st, maxit, cap, iters);
   }
@@ -410,11 +429,12 @@ static int interface_fcg(edd_problem *p, const double *rhs, double *x, int prec,
       zp = z;
     }
     const int slot = k % cap;
-    double *Pk = p->winP_d + (int64_t)slot * nG;
-    double *Qk = p->winQ_d + (int64_t)slot * nG;
+    rc = ensure_window(p, slot + 1);
+    if (rc) return rc;
+    double *Pk = win_slot(p->winP_blk, nG, slot);
+    double *Qk = win_slot(p->winQ_blk, nG, slot);
     const int m = std::min(k, cap);
-    window_orthogonalise(p, nG, p->winP_d, p->winQ_d, cap, k, m, zp, Pk,
-                         S_C_BASE, S_PQ_BASE);
+    window_orthogonalise(p, nG, cap, k, m, zp, Pk, S_C_BASE, S_PQ_BASE);
     apply_S(p, Pk, Qk, prec);
     {
       const double *a[2] = {Pk, Pk}, *b[2] = {Qk, r};
@@ -473,7 +493,8 @@ int interface_solve(edd_problem *p, const double *rhs, double *x, double rel_tol
     *iters = 0;
     return EDD_OK;
   }
-  return interface_fcg(p, rhs, x, EDD_F64, rel_tol * nr, false, o, st, maxit, 256, iters);
+  return interface_fcg(p, rhs, x, EDD_F64, rel_tol * nr, false, o, st, maxit, fcg_window(o),
+                       iters);
 }
 
 // The three steps of eq. (3MatSplit) with interior factors of precision
@@ -512,9 +533,7 @@ static int norm_f(edd_problem *p, const double *f, double *nf) {
 
 static int solve_plain(edd_problem *p, const double *f, double *u,
                        const edd_solve_opts *o, edd_solve_stats *st, double nf) {
-  const int window = o->flexible_window > 0
-                         ? o->flexible_window
-                         : (o->precond == EDD_PC_IDENTITY ? 1 : 256);
+  const int window = fcg_window(o);
   double tol_abs = o->tol * nf;
   bool guess = o->use_initial_guess != 0;
   int status = EDD_OK;
@@ -553,9 +572,7 @@ static int solve_mixed(edd_problem *p, const double *f, double *u,
   const int64_t nG = p->n_gamma * D;
   double *g = p->w_G[3], *x = p->w_G[5], *d = p->w_G[0], *r = p->w_G[6],
          *t = p->w_G[7];
-  const int window = o->flexible_window > 0
-                         ? o->flexible_window
-                         : (o->precond == EDD_PC_IDENTITY ? 1 : 256);
+  const int window = fcg_window(o);
   condense(p, f, g, EDD_F64);
   if (o->use_initial_guess) launch_gather(p, p->gnode_d, p->n_gamma, u, x);
   else launch_fill(p, nG, 0.0, x);
@@ -610,9 +627,7 @@ static int solve_relaxed(edd_problem *p, const double *f, double *u,
   const int D = p->g.dim;
   const int64_t nG = p->n_gamma * D;
   double *x = p->w_G[0], *g = p->w_G[3];
-  const int window = o->flexible_window > 0
-                         ? o->flexible_window
-                         : (o->precond == EDD_PC_IDENTITY ? 1 : 256);
+  const int window = fcg_window(o);
   condense(p, f, g, EDD_F64);
   const bool guess = o->use_initial_guess != 0;
   if (guess) launch_gather(p, p->gnode_d, p->n_gamma, u, x);

@@ -23,11 +23,15 @@ constexpr int kDirichlet = -1;
 constexpr int kCnnLayers = 4;
 constexpr int kCnnWidth = 32;
 
+// Directions of the flexible-CG window: stored in blocks of kWinBlock vectors,
+// each allocated when the iteration first reaches it, at most kMaxWindow.
+constexpr int kWinBlock = 256, kMaxWindow = 8192;
 // Scalar slots of p->scal_d (FP64 device scalars read back through the pinned
-// p->scal_h): the interface solver below 528 (api.hip), the preconditioner
-// 528..1499 (kernels_pc.hip), the OC update 1536..1599 (topopt.hip), the
-// network 1600..1605 (kernels_cnn.hip), full GMRES 2048..4095 (gmres.hip).
-constexpr int kScalTotal = 4096;
+// p->scal_h): the interface solver below 528 and its window coefficients
+// from 4096 on (api.hip), the preconditioner 528..1499 (kernels_pc.hip), the
+// OC update 1536..1599 (topopt.hip), the network 1600..1605
+// (kernels_cnn.hip), full GMRES 2048..4095 (gmres.hip).
+constexpr int kScalTotal = 4096 + 2 * kMaxWindow;
 // slots of the captured interface iteration (api.hip, kernels_vec.hip):
 // iteration index k, first converged iteration + 1 (0: not yet), tol^2,
 // r.r of the step, p.q of the step, r.r history (ring of kGHist)
@@ -243,8 +247,7 @@ struct edd_problem {
   size_t partials_len = 0;
 
   // flexible Krylov window (directions P and S P)
-  int win_cap = 0;
-  double *winP_d = nullptr, *winQ_d = nullptr;
+  std::vector<double *> winP_blk, winQ_blk;  // kWinBlock directions each
 
   // preconditioner scratch (Lanczos basis etc.)
   double *pc_d = nullptr;
