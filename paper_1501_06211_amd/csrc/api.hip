@@ -144,13 +144,28 @@ void apply_S(edd_problem *p, const double *v, double *y, int prec) {
 // directions (P) and their S images (Q), each allocated the first time the
 // iteration reaches it and kept until the handle is destroyed.
 static int ensure_window(edd_problem *p, int nslots) {
+  constexpr int kTab = kMaxWindow / kWinBlock;
   const size_t nG = (size_t)p->n_gamma * p->g.dim;
+  if (!p->win_tab_d) {
+    p->win_tab_d = (double **)dev_alloc(p, sizeof(double *) * 2 * kTab);
+    if (!p->win_tab_d) return EDD_ENOMEM;
+  }
   while ((int)p->winP_blk.size() * kWinBlock < nslots) {
     double *P = (double *)dev_alloc(p, sizeof(double) * nG * kWinBlock);
     double *Q = (double *)dev_alloc(p, sizeof(double) * nG * kWinBlock);
     if (!P || !Q) return EDD_ENOMEM;
+    const int b = (int)p->winP_blk.size();
     p->winP_blk.push_back(P);
     p->winQ_blk.push_back(Q);
+    // the kernels that read these entries are queued after the copies
+    p->win_tab_h[b] = P;
+    p->win_tab_h[kTab + b] = Q;
+    int rc = check_hip(p, hipMemcpyAsync(p->win_tab_d + b, &p->win_tab_h[b], sizeof(double *),
+                                         hipMemcpyHostToDevice, p->stream));
+    if (!rc)
+      rc = check_hip(p, hipMemcpyAsync(p->win_tab_d + kTab + b, &p->win_tab_h[kTab + b],
+                                       sizeof(double *), hipMemcpyHostToDevice, p->stream));
+    if (rc) return rc;
   }
   return EDD_OK;
 }
@@ -170,35 +185,18 @@ static int fcg_window(const edd_solve_opts *o) {
 
 // Orthogonalise z against the m newest directions of the window ring
 // (capacity cap, direction j at slot j % cap, newest at (k-1) % cap) and
-// write the result to out.  The directions go oldest first, in runs of
-// consecutive slots inside one block (at most kWinBlock, what one window
-// kernel takes): every coefficient against z first, then the combines.
+// write the result to out: every coefficient against z first (one launch
+// for the dots, one for their sums), then one combine, oldest first.
 static void window_orthogonalise(edd_problem *p, int64_t n, int cap, int k, int m,
                                  const double *z, double *out, int cbase, int dbase) {
   if (m <= 0) {
     if (out != z) launch_copy(p, n, z, out);
     return;
   }
-  constexpr int kMaxRuns = kMaxWindow / kWinBlock + 2;
-  int runs[kMaxRuns][2];
-  int nr = 0;
-  for (int t = 0; t < m && nr < kMaxRuns;) {
-    const int slot = (k - m + t) % cap;  // k >= m
-    const int len = std::min(std::min(m - t, cap - slot), kWinBlock - slot % kWinBlock);
-    runs[nr][0] = slot;
-    runs[nr][1] = len;
-    ++nr;
-    t += len;
-  }
-  for (int s = 0; s < nr; ++s)
-    launch_window_dots(p, n, runs[s][1], win_slot(p->winQ_blk, n, runs[s][0]), z,
-                       cbase + runs[s][0]);
-  const double *src = z;
-  for (int s = 0; s < nr; ++s) {
-    launch_window_combine(p, n, runs[s][1], win_slot(p->winP_blk, n, runs[s][0]),
-                          cbase + runs[s][0], dbase + runs[s][0], src, out);
-    src = out;
-  }
+  constexpr int kTab = kMaxWindow / kWinBlock;
+  const int first = (k - m) % cap;  // k >= m
+  launch_ring_dots(p, n, cap, first, m, p->win_tab_d + kTab, z, cbase);
+  launch_ring_combine(p, n, cap, first, m, p->win_tab_d, cbase, dbase, z, out);
 }
 
 // Condensation g = f_G - K_GI K_II^{-1} f_I (first two lines of eq.
@@ -877,7 +875,7 @@ int edd_setup_mesh(const edd_mesh_desc *d, const edd_allocator *a,
   for (int i = 0; i < 3; ++i) EDD_TRY_ALLOC(p->w_I[i], double, std::max<int64_t>(1, p->n_idofs));
   for (int i = 0; i < 8; ++i) EDD_TRY_ALLOC(p->w_G[i], double, std::max<int64_t>(1, p->n_gamma * D));
   for (int i = 0; i < 2; ++i) EDD_TRY_ALLOC(p->w_full[i], double, p->ndof);
-  p->partials_len = 65536 + 8192;
+  p->partials_len = std::max(65536 + 8192, kWinChunks * kMaxWindow);
   EDD_TRY_ALLOC(p->partials_d, double, p->partials_len);
   EDD_TRY_ALLOC(p->scal_d, double, S_TOTAL);
   if (hipHostMalloc((void **)&p->scal_h, sizeof(double) * S_TOTAL) != hipSuccess) {

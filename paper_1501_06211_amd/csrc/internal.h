@@ -26,6 +26,8 @@ constexpr int kCnnWidth = 32;
 // Directions of the flexible-CG window: stored in blocks of kWinBlock vectors,
 // each allocated when the iteration first reaches it, at most kMaxWindow.
 constexpr int kWinBlock = 256, kMaxWindow = 8192;
+// row chunks of the window dots (their partial sums: kWinChunks * kMaxWindow)
+constexpr int kWinChunks = 64;
 // Scalar slots of p->scal_d (FP64 device scalars read back through the pinned
 // p->scal_h): the interface solver below 528 and its window coefficients
 // from 4096 on (api.hip), the preconditioner 528..1499 (kernels_pc.hip), the
@@ -248,6 +250,10 @@ struct edd_problem {
 
   // flexible Krylov window (directions P and S P)
   std::vector<double *> winP_blk, winQ_blk;  // kWinBlock directions each
+  // device copies of the block addresses: P blocks, then Q blocks from
+  // kMaxWindow / kWinBlock on (host copy for the stream-ordered upload)
+  double **win_tab_d = nullptr;
+  double *win_tab_h[2 * edd::kMaxWindow / edd::kWinBlock] = {};
 
   // preconditioner scratch (Lanczos basis etc.)
   double *pc_d = nullptr;
@@ -393,6 +399,15 @@ void launch_window_dots_dev(edd_problem *p, int64_t n, int cap, const double *W,
                             const double *z, int cbase);
 void launch_window_combine_dev(edd_problem *p, int64_t n, int cap, const double *P,
                                int cbase, int dbase, const double *z, double *pv);
+// The same two steps in the host-driven iteration, one launch each for the
+// whole window: the m newest directions of a ring of capacity cap, oldest at
+// slot first, slot s stored at tab[s / kWinBlock] + (s % kWinBlock) * n
+// (tab a device array); dots into scal[cbase + slot].
+void launch_ring_dots(edd_problem *p, int64_t n, int cap, int first, int m,
+                      const double *const *tab, const double *z, int cbase);
+void launch_ring_combine(edd_problem *p, int64_t n, int cap, int first, int m,
+                         const double *const *tab, int cbase, int dbase, const double *z,
+                         double *pv);
 // ring[(k % cap) * n ...] = src
 void launch_ring_store(edd_problem *p, int64_t n, int cap, const double *src, double *ring);
 // end of a captured iteration: r.r into the history, p.q into

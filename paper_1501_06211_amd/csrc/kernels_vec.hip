@@ -300,6 +300,121 @@ __global__ __launch_bounds__(kBlock) void k_ring_store(int64_t n, int cap,
     ring[slot * n + i] = src[i];
 }
 
+// Window dots of the host-driven iteration over the m newest directions of
+// the ring (capacity cap, oldest at slot first), slot s stored at
+// tab[s / kWinBlock] + (s % kWinBlock) * n: partials[b*m + t] over row chunk
+// b = blockIdx.x for the eight directions t of group blockIdx.y.  Chunks,
+// loads and summation order are those of k_window_dots_dev.
+__global__ __launch_bounds__(kBlock) void k_ring_dots(
+    int64_t n, int cap, int first, int m, const double *const *__restrict__ tab,
+    const double *__restrict__ z, double *__restrict__ partials) {
+  constexpr int JB = 8, NW = kBlock / 64;
+  __shared__ double red[JB][NW];
+  const int j0 = blockIdx.y * JB;
+  const int nj = min(JB, m - j0);
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = blockIdx.x * chunk;
+  const int64_t hi = min(n, lo + chunk);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double acc[JB];
+#pragma unroll
+  for (int jj = 0; jj < JB; ++jj) acc[jj] = 0.0;
+  const double *w[JB];
+#pragma unroll
+  for (int jj = 0; jj < JB; ++jj) {
+    const int slot = (first + j0 + (jj < nj ? jj : 0)) % cap;
+    w[jj] = tab[slot / kWinBlock] + (int64_t)(slot % kWinBlock) * n;
+  }
+  int64_t i = lo + threadIdx.x;
+  for (; i + blockDim.x < hi; i += 2 * (int64_t)blockDim.x) {
+    const int64_t i1 = i + blockDim.x;
+    const double z0 = z[i], z1 = z[i1];
+    double w0[JB], w1[JB];
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj) {
+      w0[jj] = w[jj][i];
+      w1[jj] = w[jj][i1];
+    }
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj)
+      if (jj < nj) acc[jj] = fma(z1, w1[jj], fma(z0, w0[jj], acc[jj]));
+  }
+  if (i < hi) {
+    const double zi = z[i];
+#pragma unroll
+    for (int jj = 0; jj < JB; ++jj)
+      if (jj < nj) acc[jj] = fma(zi, w[jj][i], acc[jj]);
+  }
+#pragma unroll
+  for (int jj = 0; jj < JB; ++jj) {
+    double v = acc[jj];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if (lane == 0) red[jj][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nj) {
+    double s = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) s += red[threadIdx.x][w2];
+    partials[(int64_t)blockIdx.x * m + j0 + threadIdx.x] = s;
+  }
+}
+
+// scal[cbase + (first + t) % cap] = sum_b partials[b*m + t], block t < m
+// (the order of k_reduce_ring)
+__global__ __launch_bounds__(kBlock) void k_reduce_win(const double *__restrict__ partials,
+                                                       int nblocks, int m, int first, int cap,
+                                                       double *__restrict__ scal, int cbase) {
+  __shared__ double red[kBlock / 64];
+  const int t = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+    acc += partials[(int64_t)b * m + t];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) scal[cbase + (first + t) % cap] = s;
+}
+
+// pv = z - sum over the m newest directions, oldest first, of
+// (scal[cbase+slot] / scal[dbase+slot]) P_slot, the directions in LDS
+// batches of 256 (coefficient and address); per row the same chain of fmas
+// as k_window_combine_dev.
+__global__ __launch_bounds__(kBlock) void k_ring_combine(
+    int64_t n, int cap, int first, int m, const double *const *__restrict__ tab,
+    const double *__restrict__ scal, int cbase, int dbase,
+    const double *__restrict__ z, double *__restrict__ pv) {
+  constexpr int B = 256, U = 8;
+  __shared__ double coef[B];
+  __shared__ const double *ptr[B];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool live = i < n;
+    double v = live ? z[i] : 0.0;
+    for (int t0 = 0; t0 < m; t0 += B) {
+      const int len = min(B, m - t0);
+      __syncthreads();  // the previous batch's reads are done
+      for (int t = threadIdx.x; t < len; t += blockDim.x) {
+        const int slot = (first + t0 + t) % cap;
+        coef[t] = scal[cbase + slot] / scal[dbase + slot];
+        ptr[t] = tab[slot / kWinBlock] + (int64_t)(slot % kWinBlock) * n;
+      }
+      __syncthreads();
+      if (!live) continue;
+      int j = 0;
+      for (; j + U <= len; j += U) {
+        double a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = ptr[j + u][i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v = fma(-coef[j + u], a[u], v);
+      }
+      for (; j < len; ++j) v = fma(-coef[j], ptr[j][i], v);
+    }
+    if (live) pv[i] = v;
+  }
+}
+
 __global__ void k_iter_end(double *__restrict__ scal, int cap, int pqbase) {
   if (threadIdx.x != 0) return;
   const int k = (int)scal[kSlotGK];
@@ -360,6 +475,15 @@ __global__ __launch_bounds__(kBlock) void k_residual_norms(
 inline unsigned grid_for(int64_t n) {
   int64_t g = (n + kBlock - 1) / kBlock;
   if (g > kMaxBlocks) g = kMaxBlocks;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// row chunks of the flexible-CG window dots: about eight rows per thread (a
+// chunk's partial sums are few against its loads), at most kWinChunks
+inline unsigned window_chunks(int64_t n) {
+  int64_t g = (n + 8 * kBlock - 1) / (8 * kBlock);
+  if (g > kWinChunks) g = kWinChunks;
   if (g < 1) g = 1;
   return (unsigned)g;
 }
@@ -427,8 +551,7 @@ void launch_window_combine(edd_problem *p, int64_t n, int m, const double *P,
 
 void launch_window_dots_dev(edd_problem *p, int64_t n, int cap, const double *W,
                             const double *z, int cbase) {
-  unsigned g = grid_for(n);
-  if (g > 256) g = 256;
+  const unsigned g = window_chunks(n);
   k_window_dots_dev<<<dim3(g, (cap + 7) / 8), kBlock, 0, p->stream>>>(n, cap, W, z, p->scal_d,
                                                                      p->partials_d);
   k_reduce_ring<<<cap, kBlock, 0, p->stream>>>(p->partials_d, (int)g, cap, p->scal_d, cbase);
@@ -438,6 +561,23 @@ void launch_window_combine_dev(edd_problem *p, int64_t n, int cap, const double 
                                int cbase, int dbase, const double *z, double *pv) {
   k_window_combine_dev<<<grid_for(n), kBlock, 0, p->stream>>>(n, cap, P, p->scal_d, cbase,
                                                               dbase, z, pv);
+}
+
+void launch_ring_dots(edd_problem *p, int64_t n, int cap, int first, int m,
+                      const double *const *tab, const double *z, int cbase) {
+  if (m <= 0) return;
+  const unsigned g = window_chunks(n);
+  k_ring_dots<<<dim3(g, (m + 7) / 8), kBlock, 0, p->stream>>>(n, cap, first, m, tab, z,
+                                                              p->partials_d);
+  k_reduce_win<<<m, kBlock, 0, p->stream>>>(p->partials_d, (int)g, m, first, cap, p->scal_d,
+                                            cbase);
+}
+
+void launch_ring_combine(edd_problem *p, int64_t n, int cap, int first, int m,
+                         const double *const *tab, int cbase, int dbase, const double *z,
+                         double *pv) {
+  k_ring_combine<<<grid_for(n), kBlock, 0, p->stream>>>(n, cap, first, m, tab, p->scal_d, cbase,
+                                                        dbase, z, pv);
 }
 
 void launch_ring_store(edd_problem *p, int64_t n, int cap, const double *src, double *ring) {
