@@ -9,7 +9,7 @@ by repeating: (1) finite element analysis, (2) an Optimality Criteria (OC)
 density update, (3) a convergence check; the Krylov tolerance of step 1
 adapts to successive compliance values.
 
-Readings where the section is silent (stated once more in the design doc):
+Readings where the section is silent:
 * element modulus E_e = rho_e (the linear K(rho) of eq. (NumberTen)); an
   optional SIMP power p gives E_e = emin + rho_e^p (1 - emin);
 * OC update (the textbook form for a compliance objective): with
