@@ -88,3 +88,30 @@ def test_full_window_with_the_lanczos_preconditioner():
     assert np.array_equal(to_np(u2), to_np(u))
     assert st["iterations"] <= st256["iterations"] or st256["status"] != edd.OK
     prob.close()
+
+
+def test_window_block_allocation_failure_is_reported(monkeypatch):
+    """A window block that cannot be allocated ends the solve with ENOMEM
+    (forced from the host: the caching allocator behind the handle's
+    allocator is made to fail once the first block exists); with it
+    restored the same handle solves normally."""
+    require_gpu()
+    import torch
+    from paper_1501_06211_amd import edd
+    p = _thresholded(256, 128, 12.0)
+    prob = make_problem(p)
+    f = to_cuda(p.f)
+    _, st = prob.solve(f, tol=1e-7, maxit=100)  # the first block only
+    assert st["status"] == edd.NOT_CONVERGED
+
+    def no_memory(*args, **kwargs):
+        raise RuntimeError("allocation refused by the test")
+
+    with monkeypatch.context() as m:
+        m.setattr(torch.cuda, "caching_allocator_alloc", no_memory)
+        with pytest.raises(edd.EddError) as err:
+            prob.solve(f, tol=1e-7, maxit=3000)
+    assert err.value.code == edd.ENOMEM
+    u, st = prob.solve(f, tol=1e-7, maxit=3000)
+    assert st["status"] == edd.OK and st["iterations"] > 256
+    prob.close()
