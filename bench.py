@@ -342,7 +342,8 @@ def run_sequence(args, dim=3):
     thresholded (E = 1e-3 + rho^3).  The first solves (warm-started from the
     previous solution) train the correction network; on the held-out steps
     each solve is timed from the same warm start plain, with the learned
-    guess, and with the learned guess plus the relaxed mixed precision."""
+    guess, with the learned guess plus the relaxed mixed precision, and with
+    the learned guess plus a network correction step every 4th step."""
     import numpy as np
     import torch
 
@@ -390,7 +391,8 @@ def run_sequence(args, dim=3):
         for name, extra in (("plain", {}), ("learned", {"learned_guess": 1}),
                             ("learned_mixed", {"learned_guess": 1,
                                                "precision": edd.MODE_RELAXED,
-                                               "mixed_inner_tol": args.switch})):
+                                               "mixed_inner_tol": args.switch}),
+                            ("learned_corr", {"learned_guess": 1, "learned_correction": 4})):
             torch.cuda.synchronize()
             t = time.perf_counter()
             u, st = prob.solve(f, u_prev.clone(), use_initial_guess=1, **opts, **extra)
@@ -407,8 +409,8 @@ def run_sequence(args, dim=3):
     its = {n: float(np.mean([r[n][1] for r in rows])) for n in rows[0]}
     out = {
         "metric": "time to rel.res 1e-8 on held-out steps of a %s density sequence: "
-                  "plain vs learned vs learned+mixed" % ("3D 128x64x64" if dim == 3 else
-                                                         "2D 1024x512"),
+                  "plain vs learned vs learned+mixed vs learned+correction" % (
+                      "3D 128x64x64" if dim == 3 else "2D 1024x512"),
         "value": round(mean["learned_mixed"], 2), "unit": "ms", "n_gpus": 1,
         "steps": args.test, "warmup": 0, "ms_per_step": round(mean["learned_mixed"], 2),
         "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
@@ -420,6 +422,7 @@ def run_sequence(args, dim=3):
         "mean_iterations": {n: round(v, 1) for n, v in its.items()},
         "speedup_learned_mixed_vs_plain": round(mean["plain"] / mean["learned_mixed"], 3),
         "speedup_learned_vs_plain": round(mean["plain"] / mean["learned"], 3),
+        "speedup_learned_corr_vs_plain": round(mean["plain"] / mean["learned_corr"], 3),
         "training": {"seconds": round(t_train, 2), "loss_first_epoch": round(hist[0], 4),
                      "loss_last_epoch": round(hist[-1], 4)},
         "worst_rel_residual": max(r[n][2] for r in rows for n in r),
