@@ -151,9 +151,10 @@ static int ensure_window(edd_problem *p, int nslots) {
     if (!p->win_tab_d) return EDD_ENOMEM;
   }
   while ((int)p->winP_blk.size() * kWinBlock < nslots) {
-    double *P = (double *)dev_alloc(p, sizeof(double) * nG * kWinBlock);
-    double *Q = (double *)dev_alloc(p, sizeof(double) * nG * kWinBlock);
-    if (!P || !Q) return EDD_ENOMEM;
+    // one allocation per block, so a failed one leaves nothing behind
+    double *P = (double *)dev_alloc(p, sizeof(double) * 2 * nG * kWinBlock);
+    if (!P) return EDD_ENOMEM;
+    double *Q = P + nG * kWinBlock;
     const int b = (int)p->winP_blk.size();
     p->winP_blk.push_back(P);
     p->winQ_blk.push_back(Q);
