@@ -33,6 +33,32 @@ def test_pcg_and_fcg_solve_spd():
     assert abs(itf1 - itp) <= 1
 
 
+def test_fcg_keeping_every_direction_ends_within_n_steps():
+    """Section 3's flexible method with a preconditioner that changes at
+    every step (a fresh random positive diagonal): keeping every direction
+    makes each new one A-orthogonal to all earlier ones, so the iteration
+    ends within n steps, as a conjugate-direction method must; keeping only
+    the newest directions loses that on an ill-conditioned system
+    (eigenvalues from 1e-5 to 1)."""
+    n = 40
+    rng = np.random.default_rng(5)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * np.logspace(-5, 0, n)) @ Q.T
+    A = (A + A.T) / 2
+    b = rng.standard_normal(n)
+
+    def changing(seed):
+        g = np.random.default_rng(seed)
+        return lambda r: r * g.uniform(0.5, 2.0, n)
+
+    x, its, _ = krylov.fcg(lambda v: A @ v, b, changing(7), tol=1e-10, maxit=2000)
+    assert its <= n
+    assert np.linalg.norm(A @ x - b) <= 1e-10 * np.linalg.norm(b)
+    _, its1, _ = krylov.fcg(lambda v: A @ v, b, changing(7), tol=1e-10, maxit=400, mmax=1)
+    _, its20, _ = krylov.fcg(lambda v: A @ v, b, changing(7), tol=1e-10, maxit=400, mmax=20)
+    assert its1 == 400 and its20 == 400  # not converged in ten times n
+
+
 def test_gmres_right_matches_solve():
     A, b = _spd(40, 1)
     A = A + np.triu(np.ones((40, 40)), 1)  # non-symmetric
