@@ -69,8 +69,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="3d",
-                    choices=["3d", "2d", "small", "batch", "sequence", "sequence2d", "topopt"],
-                    help="batch: the 64 uneven problems solved concurrently "
+                    choices=["3d", "2d", "2d-thresholded", "small", "batch", "sequence",
+                             "sequence2d", "topopt"],
+                    help="2d-thresholded: the first field of "
+                         "the 2D 1024x512 density sequence on its own; "
+                         "batch: the 64 uneven problems solved concurrently "
                          "(solves/s and per-problem latency); sequence: a 3D "
                          "128x64x64 density sequence, network trained on the "
                          "first solves, held-out solves timed plain vs learned "
@@ -130,6 +133,12 @@ def make_workload(name):
         return workloads.cantilever3d_simp_128x64x64()
     if name == "2d":
         return workloads.cantilever2d_simp_512x256()
+    if name == "2d-thresholded":
+        # the first field of the 2D 1024x512 density sequence (E = 1e-3 + rho^3,
+        # rho thresholded at the median), 2048 subdomains of 16x16
+        w = workloads.cantilever2d(1024, 512, name="cantilever2d_thresholded_1024x512")
+        w.E = next(workloads.to_sequence_2d(1, 1024, 512))
+        return w
     return workloads.cantilever2d_uniform_64x32()
 
 

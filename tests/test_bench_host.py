@@ -20,8 +20,8 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert "one GPU" in res.stdout
 
 
-@pytest.mark.parametrize("workload", ["3d", "2d", "small", "batch", "sequence", "sequence2d",
-                                      "topopt"])
+@pytest.mark.parametrize("workload", ["3d", "2d", "2d-thresholded", "small", "batch",
+                                      "sequence", "sequence2d", "topopt"])
 def test_every_workload_parses(workload, monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", workload])
     assert bench.parse().workload == workload
